@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the read-alignment path on one MI355X.
+
+One step = snap_align over the whole read batch of the workload (all reads
+resident in HBM, index resident): seed probe, candidate gathering and dedupe,
+bounded edit-distance verification and the best / second-best call.
+
+Prints ONE JSON line: reads/s (whole job), Gbases/s, the roofline of the
+dominant kernel measured with HIP events on its launch stream during the timed
+steps, and the CPU oracle timed on a bounded sample of the same reads on the
+host cores. The GPU outputs of that sample are checked bit-exact against the
+oracle before the line is printed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane per cycle
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic bytes / ops per unit, per kernel (the design notes derive them).
+PROBE_BYTES_PER_SLOT = 128 + 32       # one 128-byte bucket line read, one 32-byte probe record written
+CAND_BYTES_PER_SLOT = 32              # probe record read back
+CAND_BYTES_PER_HIT = 4 + 12           # position read, location key + seed mask written
+CAND_BYTES_PER_READ = 4               # location count written
+VERIFY_OPS_PER_STEP = 30              # integer ops per diagonal extension (neighbour max, bounds, one 16-base compare)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--reads", type=int, default=0, help="override the read count (profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the read batch is not sharded across GPUs",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_1111_5572_amd as snapgpu
+    from synth.workloads import WORKLOADS
+
+    w = WORKLOADS[args.workload]
+    if args.reads:
+        w = w.scaled(n_reads=args.reads)
+    dev = torch.device("cuda:0")
+    snapgpu.lib()
+
+    t = time.time()
+    g = w.make_genome()
+    log(f"genome {w.name}: {len(g)} bases in {time.time() - t:.1f}s")
+    t = time.time()
+    reads = w.make_reads(g)
+    log(f"reads: {reads.n} ({int(reads.bases.shape[0])} bases) in {time.time() - t:.1f}s")
+    t = time.time()
+    gix = snapgpu.Index(g, w.params.seed_len)
+    index_s = time.time() - t
+    sizes = gix.sizes()
+    log(f"index built and resident in {index_s:.1f}s: {sizes}")
+
+    rb = torch.from_numpy(reads.bases).to(dev)
+    ln = torch.from_numpy(reads.lengths).to(dev)
+    params = snapgpu.params_from(w.params)
+    max_len = int(reads.lengths.max())
+    wb = snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), max_len, w.params.d_max, params)
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    out = snapgpu.align(gix, rb, ln, w.params.d_max, params, workspace=ws, max_len=max_len)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, max_len=max_len)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    snapgpu.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, stream=stream, max_len=max_len)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = snapgpu.profile_end()
+    ctr = snapgpu.profile_counters()
+    elapsed = t1 - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    reads_per_s = reads.n * args.steps / elapsed
+    gbases_per_s = float(reads.bases.shape[0]) * args.steps / elapsed / 1e9
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {reads_per_s:,.0f} reads/s")
+    log("kernels: " + ", ".join(f"{k} {v[1] / max(v[0], 1):.3f} ms x{v[0]}" for k, v in kern.items()))
+    log(f"counters: {ctr}")
+
+    got = out.numpy()
+    calls = np.bincount(got[4].astype(np.int64), minlength=3)
+
+    # roofline of the dominant kernel
+    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    launches, total_ms = kern[dom]
+    avg_s = total_ms / 1000.0 / launches
+    per_launch = 1.0 / launches
+    if dom == "probe":
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = ctr["seed_slots"] * PROBE_BYTES_PER_SLOT * per_launch / 1e9
+    elif dom == "candidates":
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = (ctr["seed_slots"] * CAND_BYTES_PER_SLOT + ctr["hits"] * CAND_BYTES_PER_HIT +
+                ctr["reads"] * CAND_BYTES_PER_READ) * per_launch / 1e9
+    elif dom == "verify":
+        bound, unit, peak = "alu", "TOP/s", VALU_PEAK_TOPS
+        work = ctr["lv_steps"] * VERIFY_OPS_PER_STEP * per_launch / 1e12
+    else:
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = float("nan")
+    achieved = work / avg_s
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            tr = json.load(open(args.traffic))
+            if tr.get("kernel") == dom and tr.get("workload") == w.name:
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 5), "traffic": traffic,
+                "avg_launch_ms": round(total_ms / launches, 4), "launches": launches}
+
+    # CPU oracle on a bounded sample, and a bit-exact check of that sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        t = time.time()
+        oix = oracle.Index(g, w.params.seed_len)
+        log(f"oracle index in {time.time() - t:.1f}s")
+        op = oracle.params_from(w.params)
+        rng = np.random.default_rng(7)
+        probe_n = min(reads.n, 4000)
+        idx = np.sort(rng.choice(reads.n, probe_n, replace=False))
+        sub = reads.subset(idx)
+        t = time.perf_counter()
+        res = oix.align_reads(sub, op, threads=threads)
+        dt = time.perf_counter() - t
+        rate = probe_n / max(dt, 1e-9)
+        n_s = int(min(reads.n, max(probe_n, rate * args.cpu_seconds)))
+        if n_s > probe_n:
+            idx = np.sort(rng.choice(reads.n, n_s, replace=False))
+            sub = reads.subset(idx)
+            t = time.perf_counter()
+            res = oix.align_reads(sub, op, threads=threads)
+            dt = time.perf_counter() - t
+        oix.close()
+        mism = sum(int(np.count_nonzero(np.asarray(a)[idx].astype(np.int64) != np.asarray(b).astype(np.int64)))
+                   for a, b in zip(got, res.fields()))
+        if mism:
+            print(json.dumps({"error": f"GPU output differs from the oracle on {mism} fields of the sample"}), flush=True)
+            sys.exit(1)
+        cpu = {"value": round(len(idx) / dt, 1), "unit": "reads/s", "cores": res.threads, "kind": "oracle",
+               "sample": f"{len(idx)} seeded-random reads of the {w.name} workload, {dt:.1f}s, "
+                         f"bit-exact vs GPU on all five outputs"}
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": "reads aligned/s", "value": round(reads_per_s, 1), "unit": "reads/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded genome and simulated reads; no real data)",
+        "config": {"workload": w.name, "genome_bases": len(g), "reads": reads.n,
+                   "read_len": int(reads.lengths.max()), "seed_len": w.params.seed_len,
+                   "seeds_per_read": w.params.n_min, "d_max": w.params.d_max, "conf_c": w.params.conf_c,
+                   "max_hits": w.params.max_hits},
+        "gbases_per_s": round(gbases_per_s, 4),
+        "index_build_s": round(index_s, 2), "index_device_bytes": sizes["device_bytes"],
+        "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
+        "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
+        "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    gix.close()
+
+
+if __name__ == "__main__":
+    main()

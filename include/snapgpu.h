@@ -1,0 +1,189 @@
+/*
+ * snapgpu — MI355X (gfx950) read-alignment path of SNAP (Zaharia et al.,
+ * "Faster and More Accurate Sequence Alignment with SNAP", arXiv 1111.5572).
+ *
+ * The library builds a device-resident index of every s-base seed of a genome
+ * (Section 3.1) and aligns batches of reads with Algorithm 1 (Section 3.2):
+ * seed lookup with the h_max skip, candidate gathering and dedupe, bounded edit
+ * distance verification, and the best / second-best placement call with the
+ * confidence threshold c, the 32-base result buckets and both orientations
+ * (the three aspects the paper lists as omitted from its pseudocode).
+ *
+ * Conventions for every call:
+ *  - return value: SNAP_OK (0) or a positive SNAP_E* code; snap_strerror names it;
+ *  - argument checks happen before any device work; a failed check leaves the
+ *    outputs untouched;
+ *  - the library never frees caller memory; the caller never frees index memory
+ *    except through snap_index_free.
+ */
+#ifndef SNAPGPU_H
+#define SNAPGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SNAP_OK = 0,
+    SNAP_EINVAL = 1,   /* an argument is out of range, a pointer is NULL where data is required */
+    SNAP_ENOMEM = 2,   /* host or device allocation failed, or the workspace is smaller than required */
+    SNAP_EDEVICE = 3,  /* a HIP runtime call or kernel launch failed */
+    SNAP_EBUSY = 4,    /* the server queue is full; retry later */
+    SNAP_EAGAIN = 5    /* a polled server request has not completed yet */
+};
+
+/* Name of a status code (static string, never NULL). */
+const char *snap_strerror(int code);
+
+/* ------------------------------------------------------------------ index */
+
+typedef struct snap_index snap_index;
+
+typedef struct {
+    uint64_t genome_len;      /* G, bases */
+    int32_t seed_len;         /* s */
+    int32_t reserved;
+    uint64_t windows;         /* N-free windows of length s (index entries per orientation) */
+    uint64_t distinct_keys;   /* distinct seeds up to reverse complement */
+    uint64_t table_slots;     /* slots of the open-addressing seed table (8 per 128-byte bucket) */
+    uint64_t position_entries;/* entries of the position array (windows + palindromic windows) */
+    uint64_t device_bytes;    /* HBM held by the index */
+    int32_t device;           /* HIP device ordinal the index lives on */
+    int32_t reserved2;
+} snap_index_sizes;
+
+/*
+ * Build the seed index of Section 3.1 on the current HIP device: every window
+ * of `seed_len` bases of the genome that holds no N, slid one base at a time
+ * (overlapping seeds), indexed so that a lookup returns the positions of the
+ * seed and of its reverse complement (Section 3.2, omitted aspect 2).
+ *
+ * genome:   host pointer to `len` ASCII bases; A, C, G, T in either case are
+ *           bases, every other byte is N. Copied; the caller may free it on return.
+ * len:      genome length, seed_len <= len < 2^32.
+ * seed_len: s, 1 <= s <= 32.
+ * out:      receives the index handle (device memory owned by the index).
+ * Errors:   SNAP_EINVAL (bad len or seed_len, NULL pointers), SNAP_ENOMEM,
+ *           SNAP_EDEVICE. On error *out is NULL.
+ */
+int snap_index_build(const uint8_t *genome, uint64_t len, int32_t seed_len, snap_index **out);
+
+/* Release the index and its device memory. NULL is accepted. */
+int snap_index_free(snap_index *ix);
+
+/* Sizes of a built index. */
+int snap_index_info(const snap_index *ix, snap_index_sizes *info);
+
+/* ------------------------------------------------------------ parameters */
+
+/*
+ * The five parameters of Table 3 (s is fixed by the index), plus the rules that
+ * scale n and d_max with read length L and the result bucket size:
+ *   n(L)     = min(n_cap, max(n_min, ceil(L / bp_per_seed)))   seeds to try
+ *   d_max(L) = max(d_max, ceil(d_max_pct * L / 100))            maximum distance
+ *   c        = conf_c                                           confidence threshold
+ *   h_max    = max_hits                                          max index entries per seed
+ *   bucket   = size of the position buckets whose results are merged (32 in the paper)
+ * Valid ranges: 1 <= n_min <= n_cap <= 32, bp_per_seed >= 1, conf_c >= 1,
+ * 1 <= max_hits <= 16382, 0 <= d_max_pct <= 100, bucket >= 1.
+ */
+typedef struct {
+    int32_t n_min;
+    int32_t n_cap;
+    int32_t bp_per_seed;
+    int32_t conf_c;
+    int32_t max_hits;
+    int32_t d_max_pct;
+    int32_t bucket;
+} snap_params;
+
+/* n_min 10, n_cap 32, bp_per_seed 100, c 2, h_max 300, d_max_pct 0, bucket 32. */
+snap_params snap_default_params(void);
+
+/* ----------------------------------------------------------------- align */
+
+/* Placement calls (Algorithm 1's three results). */
+enum { SNAP_NOT_FOUND = 0, SNAP_SINGLE = 1, SNAP_MULTIPLE = 2 };
+
+/*
+ * Workspace bytes snap_align needs for a batch of n_reads reads holding
+ * total_bases bases in all, the longest max_len. Any workspace of at least
+ * this size gives identical outputs; a larger one lets the library process
+ * more reads per internal pass. Returns 0 on invalid arguments.
+ */
+size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t total_bases,
+                                  int32_t max_len, int32_t d_max, const snap_params *p);
+
+/*
+ * Align a batch of reads with Algorithm 1 of Section 3.2.
+ *
+ * All array arguments are DEVICE pointers on the index's device, owned by the
+ * caller:
+ *   reads     n_reads reads concatenated, ASCII bases (uint8), sum(lengths) bytes
+ *   lengths   int32 per read, 0 <= length; reads shorter than s find no seed
+ *   pos       int64 per read: 0-based leftmost genome coordinate of the best
+ *             location (the read is reverse-complemented for strand 1), -1 if none
+ *   strand    int8 per read: 0 forward, 1 reverse complement, -1 if none
+ *   dist      int32 per read: d_best, -1 if none
+ *   second    int32 per read: d_second (best distance in any other bucket), -1 if none
+ *   call      int8 per read: SNAP_NOT_FOUND, SNAP_SINGLE or SNAP_MULTIPLE
+ *   workspace at least snap_align_workspace_bytes(...) bytes, 256-byte aligned
+ * d_max is Table 3's maximum distance (scaled per read by d_max_pct).
+ * stream is a hipStream_t (NULL = the default stream). Work is queued on it; the
+ * call may wait on the stream between internal passes, and returns once the
+ * last pass is queued. Outputs are valid after the stream is synchronized.
+ * Results do not depend on the workspace size, the batch composition or the
+ * order of reads in the batch.
+ * Errors: SNAP_EINVAL (NULL or misaligned pointers, n_reads < 0, bad params,
+ * d_max < 0, a read whose limit d_max(L) + c - 1 exceeds what the verify
+ * kernels support), SNAP_ENOMEM (workspace too small), SNAP_EDEVICE.
+ */
+int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
+               int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,
+               int32_t *second, int8_t *call, void *workspace, size_t ws_bytes, void *stream);
+
+/* Largest limit d_max(L) + c - 1 the verify kernels accept. */
+int32_t snap_max_limit(void);
+
+/* ------------------------------------------------------- instrumentation */
+
+/* Device time of one kernel of the path, summed over launches. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} snap_kernel_time;
+
+/*
+ * Per-kernel device time. After snap_profile_begin, every kernel the library
+ * launches is bracketed by a pair of HIP events recorded on its launch stream.
+ * snap_profile_end waits for those events, writes up to cap per-kernel totals
+ * (host array out, *count receives how many) and stops recording. Process-wide;
+ * not meant to be combined with concurrent callers. Returns SNAP_OK or SNAP_EDEVICE.
+ */
+int snap_profile_begin(void);
+int snap_profile_end(snap_kernel_time *out, int32_t cap, int32_t *count);
+
+/* Work counted by snap_align while profiling is on (since snap_profile_begin):
+ * the units the kernels' algorithmic bytes and operations are computed from.
+ * Collecting them adds one stream wait per internal pass. */
+typedef struct {
+    int64_t passes;       /* internal passes (chunks of reads) */
+    int64_t reads;        /* reads aligned */
+    int64_t seed_slots;   /* (read, seed slot) probe items */
+    int64_t hits;         /* seed hits gathered (h_max-passing seeds) */
+    int64_t locations;    /* distinct (strand, p) locations verified */
+    int64_t lv_steps;     /* diagonal extensions run by the verify kernel */
+    int64_t bases;        /* reserved */
+} snap_counters;
+
+int snap_profile_counters(snap_counters *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAPGPU_H */

@@ -1,0 +1,45 @@
+/*
+ * snapgpu test hooks: host-side evaluations of the library's own index layout
+ * and seed order, for checking them without a GPU. Not part of the alignment
+ * path; no device memory is touched.
+ */
+#ifndef SNAPGPU_DEBUG_H
+#define SNAPGPU_DEBUG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * Builds the seed table of snap_index_build (Section 3.1) in host memory and
+ * looks up nq seeds of seed_len ASCII bases each (queries, back to back) with
+ * the probe sequence the device uses. Per query: fwd = windows equal to the seed,
+ * rev = windows equal to its reverse complement (Section 3.2, omitted aspect 2),
+ * first_fwd = smallest forward position or -1; -1/-1/-1 for a seed holding an N.
+ * windows (may be NULL) receives the number of N-free windows. Host pointers
+ * only. Returns SNAP_OK, SNAP_EINVAL or SNAP_ENOMEM.
+ */
+int snap_debug_host_lookup(const uint8_t *genome, uint64_t len, int32_t seed_len, const uint8_t *queries,
+                           int64_t nq, int64_t *fwd, int64_t *rev, int64_t *first_fwd, uint64_t *windows);
+
+/*
+ * Offsets of the first n seeds tried for a read of length L with seed length s
+ * (Section 3.2, omitted aspect 3). out holds at least n entries (n <= 64).
+ * Returns the number written (fewer than n when the read holds fewer seeds).
+ */
+int32_t snap_debug_seed_offsets(int32_t L, int32_t s, int32_t n, int32_t *out);
+
+/*
+ * Copies `bytes` (a multiple of 4) from device src to device dst on `stream`
+ * (hipStream_t) with a plain load/store kernel: a transfer of known size for
+ * calibrating hardware byte counters. Returns SNAP_OK, SNAP_EINVAL, SNAP_EDEVICE.
+ */
+int snap_debug_copy(const void *src, void *dst, uint64_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAPGPU_DEBUG_H */

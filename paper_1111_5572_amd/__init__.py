@@ -1,0 +1,256 @@
+"""snapgpu: SNAP's read-alignment path (arXiv 1111.5572, Section 3) on MI355X.
+
+Thin ctypes binding over the C-ABI library libsnapgpu.so (declared in
+include/snapgpu.h). Every step of the path runs in the library's HIP kernels;
+this module only marshals arguments. PyTorch supplies device memory and
+streams. There is no CPU fallback: if the library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnapgpu.so")
+_lib = None
+
+SNAP_OK, SNAP_EINVAL, SNAP_ENOMEM, SNAP_EDEVICE, SNAP_EBUSY, SNAP_EAGAIN = range(6)
+NOT_FOUND, SINGLE, MULTIPLE = 0, 1, 2
+
+
+class SnapError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+class Params(ctypes.Structure):
+    """Table 3 parameters (s is fixed by the index) and the length rules."""
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("n_min", "n_cap", "bp_per_seed", "conf_c", "max_hits", "d_max_pct", "bucket")]
+
+
+class IndexSizes(ctypes.Structure):
+    _fields_ = [("genome_len", ctypes.c_uint64), ("seed_len", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("windows", ctypes.c_uint64), ("distinct_keys", ctypes.c_uint64),
+                ("table_slots", ctypes.c_uint64), ("position_entries", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "bases")]
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1111_5572_amd.build_library() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+        L.snap_strerror.argtypes = [ctypes.c_int]
+        L.snap_strerror.restype = ctypes.c_char_p
+        L.snap_index_build.argtypes = [P, u64, i32, ctypes.POINTER(P)]
+        L.snap_index_build.restype = ctypes.c_int
+        L.snap_index_free.argtypes = [P]
+        L.snap_index_free.restype = ctypes.c_int
+        L.snap_index_info.argtypes = [P, ctypes.POINTER(IndexSizes)]
+        L.snap_index_info.restype = ctypes.c_int
+        L.snap_default_params.argtypes = []
+        L.snap_default_params.restype = Params
+        L.snap_align_workspace_bytes.argtypes = [P, i64, i64, i32, i32, ctypes.POINTER(Params)]
+        L.snap_align_workspace_bytes.restype = sz
+        L.snap_align.argtypes = [P, P, P, i64, i32, ctypes.POINTER(Params), P, P, P, P, P, P, sz, P]
+        L.snap_align.restype = ctypes.c_int
+        L.snap_max_limit.argtypes = []
+        L.snap_max_limit.restype = i32
+        L.snap_debug_host_lookup.argtypes = [P, u64, i32, P, i64, P, P, P, ctypes.POINTER(u64)]
+        L.snap_debug_host_lookup.restype = ctypes.c_int
+        L.snap_debug_seed_offsets.argtypes = [i32, i32, i32, P]
+        L.snap_debug_seed_offsets.restype = i32
+        L.snap_profile_begin.argtypes = []
+        L.snap_profile_begin.restype = ctypes.c_int
+        L.snap_profile_end.argtypes = [ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
+        L.snap_profile_end.restype = ctypes.c_int
+        L.snap_profile_counters.argtypes = [ctypes.POINTER(Counters)]
+        L.snap_profile_counters.restype = ctypes.c_int
+        L.snap_debug_copy.argtypes = [P, P, u64, P]
+        L.snap_debug_copy.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().snap_strerror(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != SNAP_OK:
+        raise SnapError(code, what)
+
+
+def default_params(**kw) -> Params:
+    p = lib().snap_default_params()
+    for k, v in kw.items():
+        setattr(p, k, int(v))
+    return p
+
+
+def params_from(w) -> Params:
+    """From an object with the Table 3 fields (e.g. synth.workloads.Params)."""
+    return default_params(n_min=w.n_min, n_cap=w.n_cap, bp_per_seed=w.bp_per_seed, conf_c=w.conf_c,
+                          max_hits=w.max_hits, d_max_pct=w.d_max_pct, bucket=w.bucket)
+
+
+def max_limit() -> int:
+    return int(lib().snap_max_limit())
+
+
+def _np_u8(x) -> np.ndarray:
+    if isinstance(x, (bytes, bytearray)):
+        return np.frombuffer(bytes(x), dtype=np.uint8)
+    if isinstance(x, str):
+        return np.frombuffer(x.encode(), dtype=np.uint8)
+    return np.ascontiguousarray(x, dtype=np.uint8)
+
+
+class Index:
+    """Device-resident seed index of a genome (snap_index_build)."""
+
+    def __init__(self, genome, seed_len: int = 20):
+        g = _np_u8(genome)
+        h = ctypes.c_void_p()
+        _check(lib().snap_index_build(g.ctypes.data, g.shape[0], seed_len, ctypes.byref(h)), "snap_index_build")
+        self._h = h
+        self.seed_len = seed_len
+        self.genome_len = int(g.shape[0])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sizes(self) -> dict:
+        s = IndexSizes()
+        _check(lib().snap_index_info(self._h, ctypes.byref(s)), "snap_index_info")
+        return {n: int(getattr(s, n)) for n, _ in s._fields_ if not n.startswith("reserved")}
+
+    def close(self):
+        if self._h:
+            lib().snap_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Alignment:
+    pos: "torch.Tensor"      # int64
+    strand: "torch.Tensor"   # int8
+    dist: "torch.Tensor"     # int32
+    second: "torch.Tensor"   # int32
+    call: "torch.Tensor"     # int8
+
+    def numpy(self):
+        return tuple(t.cpu().numpy() for t in (self.pos, self.strand, self.dist, self.second, self.call))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_bytes(index: Index, n_reads: int, total_bases: int, max_len: int, d_max: int, params: Params) -> int:
+    return int(lib().snap_align_workspace_bytes(index.handle, n_reads, total_bases, max_len, d_max,
+                                                ctypes.byref(params)))
+
+
+def align(index: Index, reads, lengths, d_max: int, params: Params | None = None, out: Alignment | None = None,
+          workspace=None, stream=None, max_len: int | None = None) -> Alignment:
+    """snap_align on device tensors: reads (uint8, concatenated ASCII) and lengths
+    (int32). Returns device tensors; they are valid once `stream` is synchronized."""
+    import torch
+    params = params or default_params()
+    n = int(lengths.shape[0])
+    dev = lengths.device
+    if out is None:
+        out = Alignment(torch.empty(n, dtype=torch.int64, device=dev), torch.empty(n, dtype=torch.int8, device=dev),
+                        torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+                        torch.empty(n, dtype=torch.int8, device=dev))
+    if workspace is None:
+        ml = int(max_len) if max_len is not None else (int(lengths.max().item()) if n else 0)
+        wb = workspace_bytes(index, n, int(reads.numel()), ml, d_max, params)
+        if wb == 0 and n:
+            raise SnapError(SNAP_EINVAL, "snap_align_workspace_bytes")
+        workspace = torch.empty(max(wb, 256), dtype=torch.uint8, device=dev)
+    code = lib().snap_align(index.handle, reads.data_ptr(), lengths.data_ptr(), n, d_max, ctypes.byref(params),
+                            out.pos.data_ptr(), out.strand.data_ptr(), out.dist.data_ptr(), out.second.data_ptr(),
+                            out.call.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
+    _check(code, "snap_align")
+    return out
+
+
+# ---------------------------------------------------------------- host-only checks
+
+def debug_host_lookup(genome, seed_len: int, queries: list[str]):
+    """Build the table in host memory and look seeds up with the device's probe
+    sequence: returns (windows, [(forward hits, reverse hits, first forward hit)])."""
+    g = _np_u8(genome)
+    q = _np_u8("".join(queries))
+    nq = len(queries)
+    fwd = np.zeros(max(nq, 1), np.int64)
+    rev = np.zeros(max(nq, 1), np.int64)
+    first = np.zeros(max(nq, 1), np.int64)
+    win = ctypes.c_uint64()
+    _check(lib().snap_debug_host_lookup(g.ctypes.data, g.shape[0], seed_len, q.ctypes.data, nq, fwd.ctypes.data,
+                                        rev.ctypes.data, first.ctypes.data, ctypes.byref(win)),
+           "snap_debug_host_lookup")
+    return int(win.value), [(int(fwd[i]), int(rev[i]), int(first[i])) for i in range(nq)]
+
+
+def debug_seed_offsets(L: int, s: int, n: int) -> list[int]:
+    out = np.zeros(64, np.int32)
+    k = lib().snap_debug_seed_offsets(L, s, n, out.ctypes.data)
+    return [int(v) for v in out[:k]]
+
+
+def profile_begin():
+    _check(lib().snap_profile_begin(), "snap_profile_begin")
+
+
+def profile_end() -> dict:
+    """{kernel name: (launches, total device ms)} since profile_begin."""
+    arr = (KernelTime * 64)()
+    n = ctypes.c_int32()
+    _check(lib().snap_profile_end(arr, 64, ctypes.byref(n)), "snap_profile_end")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+
+def profile_counters() -> dict:
+    c = Counters()
+    _check(lib().snap_profile_counters(ctypes.byref(c)), "snap_profile_counters")
+    return {n: int(getattr(c, n)) for n, _ in c._fields_ if n != "bases"}
+
+
+def debug_copy(src, dst, nbytes: int, stream=None):
+    _check(lib().snap_debug_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream_ptr(stream)), "snap_debug_copy")
+
+
+def build_library(force: bool = True) -> str:
+    """Compile libsnapgpu.so for gfx950 (see build.py)."""
+    from .build import build as _b
+    return _b(force=force)

@@ -1,0 +1,38 @@
+"""Compile the HIP library (libsnapgpu.so) for gfx950 with hipcc, in-tree."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("index.hip", "align.hip")]
+HEADERS = [os.path.join(HERE, "csrc", "snap_internal.h"), os.path.join(ROOT, "include", "snapgpu.h")]
+LIB = os.path.join(HERE, "libsnapgpu.so")
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # packed fp32 instructions off for all device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    """Compile every source into libsnapgpu.so (always recompiles unless force=False
+    and the library is newer than every source)."""
+    if not force and os.path.exists(LIB):
+        newest = max(os.path.getmtime(f) for f in SOURCES + HEADERS)
+        if os.path.getmtime(LIB) >= newest:
+            return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *SOURCES]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

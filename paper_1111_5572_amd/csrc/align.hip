@@ -1,0 +1,1038 @@
+// Alignment path of Algorithm 1 (Section 3.2) on gfx950, as a pipeline of kernels
+// per pass over a chunk of reads:
+//
+//   pack       ASCII reads -> 2-bit stream + 1-bit N mask (once per batch)
+//   probe      every seed slot of every read: seed code, reverse complement,
+//              canonical code, one 128-byte bucket read by 8 cooperating lanes,
+//              h_max test; writes the forward / reverse hit lists of the seed
+//   hitcount   per read: hits of the seeds that pass the h_max test
+//   candidates per read: hits -> locations (strand, p), deduplicated into a
+//              sorted list with one bit per seed that voted for it
+//   compact    per read: sorted lists packed back to back
+//   verify     per location: bounded edit distance with limit K = d_max + c - 1
+//              (Landau-Vishkin furthest-reaching diagonals, one lane per
+//              location, read and window staged in LDS)
+//   replay     per read: Algorithm 1's control flow over the seed masks and the
+//              capped distances, with the exact d_limit of every step
+//
+// Why verifying every location once with limit K and replaying gives the same
+// result as the sequential algorithm: every d_limit Algorithm 1 can use is at most
+// K (d_max + c - 1 when d_best > d_max; d_best + c - 1 <= K when d_best <= d_max;
+// d_best - 1 < K otherwise), so EditDistance(p, limit) equals min(D, K+1) when
+// that is at most the limit and the special value otherwise. The seed masks give
+// the vote count of a location after seeds 1..i as popcount(mask & prefix_i).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/snapgpu.h"
+#include "../../include/snapgpu_debug.h"
+#include "snap_internal.h"
+
+using namespace snapgpu;
+
+namespace {
+
+constexpr int ST_NONE = 0;   // slot beyond the read's seeds
+constexpr int ST_N = 1;      // seed holds an N: not looked up
+constexpr int ST_OVER = 2;   // more than h_max index entries: skipped
+constexpr int ST_OK = 3;     // looked up (possibly with no hits)
+constexpr int DINF = 0x3FFF;
+constexpr int STREAM_GUARD = 32;   // bases of padding before the packed read stream
+constexpr int64_t CHUNK_READS = 1 << 20;
+constexpr int VERIFY_KMAX = 63;
+constexpr int VERIFY_LMAX = 2048;
+
+struct ProbeRec {
+    uint64_t off_f;   // first forward hit (positions index)
+    uint64_t off_r;   // first reverse hit
+    uint32_t nf;      // forward hits of the seed
+    uint32_t nr;      // reverse hits of the seed
+    uint16_t o;       // seed offset in the read
+    uint8_t status;
+    uint8_t pad[5];
+};
+static_assert(sizeof(ProbeRec) == 32, "probe record is two 16-byte words");
+
+struct Shifts {
+    int32_t n;
+    int8_t v[32];
+};
+
+struct Rule {
+    int32_t s, n_min, n_cap, bp_per_seed, c, hmax, dmax, dmax_pct, bucket;
+};
+
+__host__ __device__ inline int seeds_for_length(const Rule &r, int L) {
+    int want = (L + r.bp_per_seed - 1) / r.bp_per_seed;
+    return want < r.n_min ? r.n_min : (want > r.n_cap ? r.n_cap : want);
+}
+
+__host__ __device__ inline int dmax_for_length(const Rule &r, int L) {
+    int pct = (int)(((int64_t)r.dmax_pct * L + 99) / 100);
+    return pct > r.dmax ? pct : r.dmax;
+}
+
+// Offset of seed i (0-based) of a read of length L under the shift order, or -1.
+__host__ __device__ inline int seed_offset(const Shifts &sh, int s, int L, int i) {
+    for (int k = 0; k < sh.n; k++) {
+        int phi = sh.v[k];
+        int cnt = (phi + s <= L) ? (L - s - phi) / s + 1 : 0;
+        if (i < cnt) return phi + i * s;
+        i -= cnt;
+    }
+    return -1;
+}
+
+// Shift order of the seed schedule (Section 3.2, omitted aspect 3): 0, s/2, then
+// s/4 and 3s/4, then odd multiples of s/8 ..., floored, repeats dropped.
+Shifts make_shifts(int s) {
+    Shifts sh{};
+    bool used[32] = {false};
+    sh.v[sh.n++] = 0;
+    used[0] = true;
+    for (int level = 1; sh.n < s && level < 31; level++) {
+        int64_t den = 1ll << level;
+        for (int64_t j = 1; j < den && sh.n < s; j += 2) {
+            int v = (int)((int64_t)s * j / den);
+            if (!used[v]) { used[v] = true; sh.v[sh.n++] = (int8_t)v; }
+        }
+    }
+    return sh;
+}
+
+// ------------------------------------------------------------ bit helpers
+
+__device__ inline uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
+    return __builtin_amdgcn_alignbit(hi, lo, sh);   // (hi:lo) >> sh, sh in [0, 31]
+}
+
+// 16 bases from a 2-bit array starting at base x
+__device__ inline uint32_t ext_code16(const uint32_t *a, int64_t x) {
+    int64_t w = x >> 4;
+    return funnel(a[w + 1], a[w], (uint32_t)(x & 15) * 2);
+}
+
+// 16 N flags from a 1-bit array starting at base x
+__device__ inline uint32_t ext_mask16(const uint32_t *a, int64_t x) {
+    int64_t w = x >> 5;
+    return funnel(a[w + 1], a[w], (uint32_t)(x & 31)) & 0xFFFFu;
+}
+
+// bit k of a 16-bit mask -> bit 2k
+__device__ inline uint32_t spread16(uint32_t m) {
+    m = (m | (m << 8)) & 0x00FF00FFu;
+    m = (m | (m << 4)) & 0x0F0F0F0Fu;
+    m = (m | (m << 2)) & 0x33333333u;
+    m = (m | (m << 1)) & 0x55555555u;
+    return m;
+}
+
+// reverse complement of 16 bases in a word
+__device__ inline uint32_t rc16(uint32_t w) {
+    uint32_t r = __builtin_bitreverse32(w);
+    r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+    return ~r;
+}
+
+__device__ inline int base_code(uint8_t b) {
+    switch (b) {
+        case 'A': case 'a': return 0;
+        case 'C': case 'c': return 1;
+        case 'G': case 'g': return 2;
+        case 'T': case 't': return 3;
+        default: return 4;
+    }
+}
+
+// ------------------------------------------------------------------ pack
+
+// Stream base x (x = STREAM_GUARD + global base index). Block t of 32 bases owns
+// code words 2t, 2t+1 and mask word t. Bases outside the reads are N.
+__global__ void k_pack(const uint8_t *reads, int64_t B, uint32_t *rcode, uint32_t *rmask, int64_t nblk) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblk) return;
+    uint32_t c0 = 0, c1 = 0, m = 0;
+    for (int k = 0; k < 32; k++) {
+        int64_t g = t * 32 + k - STREAM_GUARD;
+        int c = (g >= 0 && g < B) ? base_code(reads[g]) : 4;
+        if (c > 3) { m |= 1u << k; c = 0; }
+        if (k < 16) c0 |= (uint32_t)c << (2 * k); else c1 |= (uint32_t)c << (2 * (k - 16));
+    }
+    rcode[2 * t] = c0;
+    rcode[2 * t + 1] = c1;
+    rmask[t] = m;
+}
+
+__global__ void k_maxlen(const int32_t *len, int64_t n, uint32_t *out) {
+    __shared__ uint32_t red[256];
+    uint32_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int v = len[i];
+        uint32_t u = v < 0 ? 0x80000000u : (uint32_t)v;   // negative lengths flagged
+        m = m > u ? m : u;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, red[0]);
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ----------------------------------------------------------------- probe
+
+struct ProbeArgs {
+    DevIndex ix;
+    const uint32_t *rcode, *rmask;
+    const int64_t *roff;   // global read offsets (bases)
+    const int32_t *len;
+    int64_t r0, nr;        // chunk: reads [r0, r0 + nr)
+    int32_t NS;            // seed slots per read
+    Rule rule;
+    Shifts sh;
+    ProbeRec *out;         // nr * NS records
+};
+
+// Eight lanes per (read, seed slot): each lane reads one 16-byte slot of the
+// seed's 128-byte bucket, so one probe is one coalesced cache-line read.
+__global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t item = gt >> 3;
+    const int sub = (int)(gt & 7);
+    const int lane = threadIdx.x & 63;
+    const int s = a.ix.s;
+    const bool valid = item < a.nr * (int64_t)a.NS;
+    int64_t r = valid ? item / a.NS : 0;
+    int i = valid ? (int)(item % a.NS) : 0;
+    int L = valid ? a.len[a.r0 + r] : 0;
+    int o = -1;
+    if (valid && i < seeds_for_length(a.rule, L)) o = seed_offset(a.sh, s, L, i);
+    int status = ST_NONE;
+    uint64_t key = 0, canon = 0;
+    if (o >= 0) {
+        const int64_t x = STREAM_GUARD + a.roff[a.r0 + r] + o;
+        const int64_t w = x >> 4;
+        const uint32_t sh = (uint32_t)(x & 15) * 2;
+        uint64_t lo = (uint64_t)a.rcode[w] | ((uint64_t)a.rcode[w + 1] << 32);
+        uint64_t hi = a.rcode[w + 2];
+        key = (lo >> sh) | (sh ? (hi << (64 - sh)) : 0);
+        key &= seed_mask(s);
+        const int64_t mw = x >> 5;
+        uint64_t m64 = (uint64_t)a.rmask[mw] | ((uint64_t)a.rmask[mw + 1] << 32);
+        uint64_t nbits = (m64 >> (x & 31)) & (s >= 32 ? 0xFFFFFFFFull : ((1ull << s) - 1));
+        if (nbits) status = ST_N;
+        else {
+            status = ST_OK;
+            uint64_t rc = rc_code(key, s);
+            canon = key < rc ? key : rc;
+        }
+    }
+    bool pending = (status == ST_OK);
+    uint64_t b = pending ? home_bucket(canon, a.ix.log2_buckets) : 0;
+    uint64_t val = 0;
+    bool found = false, writer = (sub == 0) && !pending;
+    uint64_t steps = 0;
+    // every group runs until its probe ends; the loop is uniform over the wave.
+    // The table is at most 70% full, so an empty slot ends every probe; the step
+    // bound only guarantees termination on a corrupted table.
+    for (;;) {
+        uint64_t k0 = EMPTY_KEY, v0 = 0;
+        if (pending) {
+            const uint64_t slot = b * SLOTS_PER_BUCKET + sub;
+            const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(a.ix.table + 2 * slot);
+            k0 = e.x;
+            v0 = e.y;
+        }
+        const uint64_t hit = __ballot(pending && k0 == canon);
+        const uint64_t emp = __ballot(pending && k0 == EMPTY_KEY);
+        const int g0 = lane & ~7;
+        const uint32_t ghit = (uint32_t)(hit >> g0) & 0xFFu, gemp = (uint32_t)(emp >> g0) & 0xFFu;
+        if (pending) {
+            if (ghit) {
+                // the lane holding the key writes the record
+                if (sub == __builtin_ctz(ghit)) { found = true; val = v0; writer = true; }
+                pending = false;
+            } else if (gemp) {
+                writer = (sub == 0);
+                pending = false;
+            } else {
+                b = (b + 1) & (a.ix.nbuckets - 1);
+                if (++steps >= a.ix.nbuckets) { writer = (sub == 0); pending = false; }
+            }
+        }
+        if (__ballot(pending) == 0) break;
+    }
+    if (!valid || !writer) return;
+    ProbeRec rec{};
+    rec.status = (uint8_t)status;
+    rec.o = (uint16_t)(o < 0 ? 0 : o);
+    if (status == ST_OK && found) {
+        const uint64_t off = val & OFF_MASK;
+        const uint32_t nf = (uint32_t)((val >> 36) & CNT_SAT), nrv = (uint32_t)((val >> 50) & CNT_SAT);
+        if ((int64_t)nf + nrv > a.rule.hmax) {
+            rec.status = ST_OVER;
+        } else if (key == canon) {
+            rec.off_f = off; rec.nf = nf; rec.off_r = off + nf; rec.nr = nrv;
+        } else {   // the seed is the reverse complement of the stored key
+            rec.off_f = off + nf; rec.nf = nrv; rec.off_r = off; rec.nr = nf;
+        }
+    }
+    a.out[item] = rec;
+}
+
+// ------------------------------------------------------------ candidates
+
+__global__ void k_hitcount(const ProbeRec *pr, int64_t nr, int NS, uint32_t *hits) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    uint32_t h = 0;
+    for (int i = 0; i < NS; i++) {
+        const ProbeRec &p = pr[r * NS + i];
+        if (p.status == ST_OK) h += p.nf + p.nr;
+    }
+    hits[r] = h;
+}
+
+struct CandArgs {
+    const ProbeRec *pr;
+    int32_t NS;
+    const uint32_t *positions;
+    uint64_t G;
+    int32_t s;
+    const int32_t *len;
+    int64_t r0, nr;
+    const int64_t *hoff;     // reserved region per read
+    uint64_t *key;           // p << 1 | strand, sorted per read
+    uint32_t *mask;          // seeds that voted
+    uint32_t *count;         // distinct locations per read
+};
+
+__device__ inline void cand_insert(uint64_t *key, uint32_t *mask, int64_t base, uint32_t &C, uint64_t k,
+                                   uint32_t bit) {
+    uint32_t lo = 0, hi = C;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (key[base + mid] < k) lo = mid + 1; else hi = mid;
+    }
+    if (lo < C && key[base + lo] == k) {
+        mask[base + lo] |= bit;
+        return;
+    }
+    for (uint32_t j = C; j > lo; j--) {
+        key[base + j] = key[base + j - 1];
+        mask[base + j] = mask[base + j - 1];
+    }
+    key[base + lo] = k;
+    mask[base + lo] = bit;
+    C++;
+}
+
+// Algorithm 1's vote loop: a forward hit q of the seed at offset o votes for
+// (+, q - o); a reverse hit for (-, q - (L - o - s)); locations outside
+// [0, G - L] are dropped.
+__global__ void k_candidates(CandArgs a) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.nr) return;
+    const int64_t L = a.len[a.r0 + r];
+    const int64_t base = a.hoff[r];
+    uint32_t C = 0;
+    for (int i = 0; i < a.NS; i++) {
+        const ProbeRec p = a.pr[r * a.NS + i];
+        if (p.status != ST_OK) continue;
+        const uint32_t bit = 1u << i;
+        for (uint32_t j = 0; j < p.nf; j++) {
+            int64_t q = a.positions[p.off_f + j];
+            int64_t pp = q - p.o;
+            if (pp >= 0 && pp + L <= (int64_t)a.G) cand_insert(a.key, a.mask, base, C, (uint64_t)pp << 1, bit);
+        }
+        for (uint32_t j = 0; j < p.nr; j++) {
+            int64_t q = a.positions[p.off_r + j];
+            int64_t pp = q - (L - p.o - a.s);
+            if (pp >= 0 && pp + L <= (int64_t)a.G) cand_insert(a.key, a.mask, base, C, ((uint64_t)pp << 1) | 1, bit);
+        }
+    }
+    a.count[r] = C;
+}
+
+__global__ void k_compact(const int64_t *hoff, const int64_t *coff, const uint32_t *count, int64_t nr,
+                          const uint64_t *key_in, const uint32_t *mask_in, uint64_t *key_out, uint32_t *mask_out,
+                          uint32_t *cread) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const int64_t src = hoff[r], dst = coff[r];
+    const uint32_t C = count[r];
+    for (uint32_t k = 0; k < C; k++) {
+        key_out[dst + k] = key_in[src + k];
+        mask_out[dst + k] = mask_in[src + k];
+        cread[dst + k] = (uint32_t)r;
+    }
+}
+
+// ----------------------------------------------------------------- verify
+
+struct VerifyArgs {
+    const uint32_t *gcode, *gmask;
+    uint64_t G;
+    const uint32_t *rcode, *rmask;
+    const int64_t *roff;
+    const int32_t *len;
+    int64_t r0;
+    const uint64_t *key;
+    const uint32_t *cread;
+    const int64_t *ncand_ptr;   // number of locations (device scalar)
+    Rule rule;
+    int32_t RW, TW;             // staged words per lane (read, text), guard word included
+    uint8_t *dcap;
+    uint32_t *steps;            // per-location diagonal extensions (profiling only, else null)
+};
+
+// Per-lane LDS arrays are laid out [word][lane], so a wave's accesses to its
+// lanes' arrays hit 64 distinct banks whatever word each lane needs.
+struct Stage {
+    uint32_t *RC, *RN, *TC, *TN;
+    int16_t *FR;
+    int lane;
+    __device__ inline uint32_t r16(int i) const {
+        int w = i >> 4;
+        return funnel(RC[(w + 1) * 64 + lane], RC[w * 64 + lane], (uint32_t)(i & 15) * 2);
+    }
+    __device__ inline uint32_t rn16(int i) const {
+        int w = i >> 4;
+        return funnel(RN[(w + 1) * 64 + lane], RN[w * 64 + lane], (uint32_t)(i & 15) * 2);
+    }
+    __device__ inline uint32_t t16(int j) const {
+        int w = j >> 4;
+        return funnel(TC[(w + 1) * 64 + lane], TC[w * 64 + lane], (uint32_t)(j & 15) * 2);
+    }
+    __device__ inline uint32_t tn16(int j) const {
+        int w = j >> 4;
+        return funnel(TN[(w + 1) * 64 + lane], TN[w * 64 + lane], (uint32_t)(j & 15) * 2);
+    }
+};
+
+// Extend a diagonal: from read row i on diagonal d (text column i + d), advance
+// while read and text bases are equal (N equals nothing), 16 bases per step.
+__device__ inline int slide(const Stage &st, int i, int d, int L, int Tn) {
+    for (;;) {
+        const int j = i + d;
+        const int rem = min(L - i, Tn - j);
+        if (rem <= 0) return i;
+        const uint32_t x = st.r16(i) ^ st.t16(j);
+        uint32_t m = ((x | (x >> 1)) & 0x55555555u) | st.rn16(i) | st.tn16(j);
+        if (rem < 16) m |= 0xFFFFFFFFu << (2 * rem);
+        if (m == 0) { i += 16; continue; }
+        return i + (int)(__builtin_ctz(m) >> 1);
+    }
+}
+
+// Bounded edit distance (Section 3.2): D = min over j of Lev(read', text[0, j)),
+// start anchored at p, end free, read' the read or its reverse complement.
+// Furthest-reaching rows per diagonal, e = 0, 1, ..., limit; returns D if D <= K,
+// else K + 1.
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
+    extern __shared__ uint32_t sm[];
+    const int lane = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+    if (k >= *a.ncand_ptr) return;
+    Stage st;
+    st.lane = lane;
+    st.RC = sm;
+    st.RN = st.RC + a.RW * 64;
+    st.TC = st.RN + a.RW * 64;
+    st.TN = st.TC + a.TW * 64;
+    st.FR = reinterpret_cast<int16_t *>(st.TN + a.TW * 64);
+
+    const uint64_t key = a.key[k];
+    const int64_t p = (int64_t)(key >> 1);
+    const int strand = (int)(key & 1);
+    const int64_t r = a.cread[k];
+    const int L = a.len[a.r0 + r];
+    const int K = dmax_for_length(a.rule, L) + a.rule.c - 1;
+    const int64_t xb = STREAM_GUARD + a.roff[a.r0 + r];
+    const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
+
+    const int nrw = (L + 15) >> 4;
+    for (int w = 0; w < nrw; w++) {
+        uint32_t c, n;
+        if (strand == 0) {
+            c = ext_code16(a.rcode, xb + 16 * w);
+            n = ext_mask16(a.rmask, xb + 16 * w);
+        } else {
+            const int64_t x = xb + L - 16 * (w + 1);
+            c = rc16(ext_code16(a.rcode, x));
+            n = __builtin_bitreverse32(ext_mask16(a.rmask, x)) >> 16;
+        }
+        st.RC[w * 64 + lane] = c;
+        st.RN[w * 64 + lane] = spread16(n);
+    }
+    st.RC[nrw * 64 + lane] = 0;
+    st.RN[nrw * 64 + lane] = 0;
+    const int ntw = (Tn + 15) >> 4;
+    for (int w = 0; w < ntw; w++) {
+        st.TC[w * 64 + lane] = ext_code16(a.gcode, p + 16 * w);
+        st.TN[w * 64 + lane] = spread16(ext_mask16(a.gmask, p + 16 * w));
+    }
+    st.TC[ntw * 64 + lane] = 0;
+    st.TN[ntw * 64 + lane] = 0;
+
+    constexpr int NEG = -30000;
+    int D = K + 1;
+    uint32_t nsteps = 1;
+    const int i0 = slide(st, 0, 0, L, Tn);
+    if (i0 >= L) {
+        D = 0;
+    } else {
+        for (int t = 0; t < 2 * KMAX + 3; t++) st.FR[t * 64 + lane] = (int16_t)NEG;
+        st.FR[(KMAX + 1) * 64 + lane] = (int16_t)i0;
+        for (int e = 1; e <= K; e++) {
+            int left = NEG;   // previous round's value on diagonal d - 1
+            bool done = false;
+            for (int d = -e; d <= e; d++) {
+                const int idx = d + KMAX + 1;
+                const int od = st.FR[idx * 64 + lane], orr = st.FR[(idx + 1) * 64 + lane];
+                int i = max(left, max(od, orr) + 1);
+                left = od;
+                i = min(i, min(L, Tn - d));
+                if (i >= max(0, -d)) {
+                    nsteps++;
+                    i = slide(st, i, d, L, Tn);
+                    if (i >= L) done = true;
+                } else {
+                    i = NEG;
+                }
+                st.FR[idx * 64 + lane] = (int16_t)i;
+                if (done) break;
+            }
+            if (done) { D = e; break; }
+        }
+    }
+    a.dcap[k] = (uint8_t)D;
+    if (a.steps) a.steps[k] = nsteps;
+}
+
+__global__ void k_sum_u32(const uint32_t *v, const int64_t *n_ptr, unsigned long long *out) {
+    __shared__ unsigned long long red[256];
+    const int64_t n = *n_ptr;
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += v[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// ----------------------------------------------------------------- replay
+
+struct ReplayArgs {
+    const ProbeRec *pr;
+    int32_t NS;
+    const uint64_t *key;
+    const uint32_t *mask;
+    const uint8_t *dcap;
+    const int64_t *coff;
+    const uint32_t *count;
+    uint64_t *bmin;
+    uint8_t *scored;
+    const int32_t *len;
+    int64_t r0, nr;
+    Rule rule;
+    int64_t *pos;
+    int8_t *strand;
+    int32_t *dist, *second;
+    int8_t *call;
+};
+
+struct ReadState {
+    int d_best, d_second;
+    int64_t best_p;
+    int best_s;
+    int64_t best_rep;
+};
+
+__device__ inline bool lex_less(int d1, int64_t p1, int s1, int d2, int64_t p2, int s2) {
+    return d1 < d2 || (d1 == d2 && (p1 < p2 || (p1 == p2 && s1 < s2)));
+}
+
+// Score location k (Algorithm 1's EditDistance call, from its capped distance)
+// and merge the result into its bucket (Section 3.2, omitted aspect 1).
+__device__ inline void replay_score(const ReplayArgs &a, int64_t base, int64_t k, int dmax, ReadState &st) {
+    const int c = a.rule.c;
+    int lim;
+    if (st.d_best > dmax) lim = dmax + c - 1;
+    else if (st.d_second >= st.d_best + c) lim = st.d_best + c - 1;
+    else lim = st.d_best - 1;
+    const int dc = a.dcap[base + k];
+    a.scored[base + k] = 1;
+    if (dc > lim) return;   // the special value: scored, never wins
+    const uint64_t kk = a.key[base + k];
+    const int64_t p = (int64_t)(kk >> 1);
+    const int s = (int)(kk & 1);
+    const int64_t bk = p / a.rule.bucket;
+    // bucket representative: first location of the same strand in the bucket
+    int64_t j = k;
+    while (j > 0 && (int64_t)(a.key[base + j - 1] >> 1) / a.rule.bucket == bk) j--;
+    while (j < k && (int)(a.key[base + j] & 1) != s) j++;
+    const uint64_t nv0 = ((uint64_t)dc << 32) | (uint64_t)p;
+    const uint64_t old = a.bmin[base + j];
+    const uint64_t nv = nv0 < old ? nv0 : old;
+    a.bmin[base + j] = nv;
+    const int vd = (int)(nv >> 32);
+    const int64_t vp = (int64_t)(nv & 0xFFFFFFFFull);
+    if (st.best_rep == j) {
+        st.d_best = vd;
+        st.best_p = vp;
+    } else if (st.best_rep < 0 || lex_less(vd, vp, s, st.d_best, st.best_p, st.best_s)) {
+        st.d_second = st.best_rep < 0 ? DINF : st.d_best;
+        st.d_best = vd;
+        st.best_p = vp;
+        st.best_s = s;
+        st.best_rep = j;
+    } else if (vd < st.d_second) {
+        st.d_second = vd;
+    }
+}
+
+__global__ void k_replay(ReplayArgs a) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.nr) return;
+    const int L = a.len[a.r0 + r];
+    const int dmax = dmax_for_length(a.rule, L), c = a.rule.c;
+    const int64_t base = a.coff[r];
+    const uint32_t C = a.count[r];
+    for (uint32_t k = 0; k < C; k++) {
+        a.scored[base + k] = 0;
+        a.bmin[base + k] = ~0ull;
+    }
+    ReadState st{DINF, DINF, -1, -1, -1};
+    const int round0 = L / a.rule.s;
+    int t = 0, call = -1;
+    bool looked = false, all_over = true;
+    uint32_t prefix = 0;
+    for (int i = 0; i < a.NS && call < 0; i++) {
+        const int status = a.pr[r * a.NS + i].status;
+        if (status == ST_NONE) break;
+        if (status == ST_N) continue;
+        looked = true;
+        if (status == ST_OVER) continue;
+        all_over = false;
+        prefix |= 1u << i;
+        if (i < round0) t++;
+        // the unscored location with the most seeds hitting; ties to smaller p, then +
+        int64_t kb = -1;
+        int bc = 0;
+        for (uint32_t k = 0; k < C; k++) {
+            const uint32_t m = a.mask[base + k] & prefix;
+            if (!m || a.scored[base + k]) continue;
+            const int cnt = __builtin_popcount(m);
+            if (cnt > bc) { bc = cnt; kb = k; }
+        }
+        if (kb >= 0) replay_score(a, base, kb, dmax, st);
+        if (st.d_best < c && st.d_second < st.d_best + c) {
+            call = SNAP_MULTIPLE;
+        } else if (st.d_best < DINF && t >= st.d_best + c) {
+            // score the remaining locations in selection order (counts are frozen)
+            for (int cnt = __builtin_popcount(prefix); cnt >= 1; cnt--)
+                for (uint32_t k = 0; k < C; k++) {
+                    if (a.scored[base + k]) continue;
+                    if (__builtin_popcount(a.mask[base + k] & prefix) == cnt) replay_score(a, base, k, dmax, st);
+                }
+            break;
+        }
+    }
+    if (call < 0) {
+        if (st.d_best <= dmax && st.d_second >= st.d_best + c) call = SNAP_SINGLE;
+        else if (st.d_best <= dmax || (looked && all_over)) call = SNAP_MULTIPLE;
+        else call = SNAP_NOT_FOUND;
+    }
+    const int64_t g = a.r0 + r;
+    const bool has = st.d_best < DINF;
+    a.pos[g] = has ? st.best_p : -1;
+    a.strand[g] = (int8_t)(has ? st.best_s : -1);
+    a.dist[g] = has ? st.d_best : -1;
+    a.second[g] = st.d_second < DINF ? st.d_second : -1;
+    a.call[g] = (int8_t)call;
+}
+
+// For each read in the chunk, the largest prefix [0, k) whose reserved region fits.
+__global__ void k_fit(const int64_t *hoff, int64_t nr, int64_t cap, int64_t *out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nr) return;
+    if (hoff[k + 1] > cap && hoff[k] <= cap) *out = k;
+}
+
+// ------------------------------------------------------------------ host
+
+struct CastLen {
+    const int32_t *len;
+    int64_t n;
+    __host__ __device__ int64_t operator()(int64_t i) const { return i < n ? (int64_t)len[i] : 0; }
+};
+struct CastU32 {
+    const uint32_t *v;
+    int64_t n;
+    __host__ __device__ int64_t operator()(int64_t i) const { return i < n ? (int64_t)v[i] : 0; }
+};
+
+template <class F>
+hipError_t scan_excl(void *tmp, size_t &tmp_bytes, F f, int64_t items, int64_t *out, hipStream_t st) {
+    hipcub::CountingInputIterator<int64_t> ci(0);
+    hipcub::TransformInputIterator<int64_t, F, hipcub::CountingInputIterator<int64_t>> it(ci, f);
+    return hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, it, out, (int)items, st);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    // batch part
+    size_t off_roff, off_rcode, off_rmask, off_misc;
+    // chunk part
+    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan;
+    size_t off_pool;
+    int64_t R;             // reads per chunk
+    int64_t pool_slots;    // reserved location slots per chunk
+    size_t total;
+};
+
+constexpr size_t POOL_SLOT_BYTES = 8 + 4 + 8 + 4 + 4 + 1 + 8 + 1;   // see the carve list in snap_align
+
+size_t scan_tmp_bytes(int64_t items) {
+    size_t b = 0;
+    CastLen f{nullptr, 0};
+    scan_excl(nullptr, b, f, items, nullptr, 0);
+    return b;
+}
+
+Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t pool_slots) {
+    Layout l{};
+    size_t o = 0;
+    l.off_roff = o; o = align256(o + sizeof(int64_t) * (size_t)(n + 1));
+    const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
+    l.off_rcode = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)nblk);
+    l.off_rmask = o; o = align256(o + sizeof(uint32_t) * (size_t)nblk);
+    l.off_misc = o; o = align256(o + 64);
+    l.R = R;
+    l.off_probe = o; o = align256(o + sizeof(ProbeRec) * (size_t)R * NS);
+    l.off_hits = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
+    l.off_hoff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
+    l.off_ccount = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
+    l.off_coff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
+    l.off_scan = o; o = align256(o + std::max(scan_tmp_bytes(R + 1), scan_tmp_bytes(n + 1)));
+    int64_t minslots = (int64_t)NS * hmax;
+    if (pool_slots < minslots) pool_slots = minslots;
+    l.pool_slots = pool_slots;
+    l.off_pool = o; o = align256(o + POOL_SLOT_BYTES * (size_t)pool_slots + 8 * 256);
+    l.total = o;
+    return l;
+}
+
+bool valid_params(const snap_params *p) {
+    return p && p->n_min >= 1 && p->n_cap >= p->n_min && p->n_cap <= MAX_SEEDS && p->bp_per_seed >= 1 &&
+           p->conf_c >= 1 && p->max_hits >= 1 && p->max_hits <= MAX_HITS_LIMIT && p->d_max_pct >= 0 &&
+           p->d_max_pct <= 100 && p->bucket >= 1;
+}
+
+Rule make_rule(const snap_index *ix, int32_t d_max, const snap_params *p) {
+    return Rule{ix->d.s, p->n_min, p->n_cap, p->bp_per_seed, p->conf_c, p->max_hits, d_max, p->d_max_pct, p->bucket};
+}
+
+#define HIP_OK(x) do { if ((x) != hipSuccess) return SNAP_EDEVICE; } while (0)
+
+// Optional per-kernel device time: an event pair recorded on the launch stream
+// around every kernel while profiling is on.
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof;
+bool g_prof_on = false;
+snap_counters g_ctr;
+
+template <class Launch>
+void timed(const char *name, hipStream_t st, Launch launch) {
+    if (!g_prof_on) { launch(); return; }
+    ProfRec r{name, nullptr, nullptr};
+    (void)hipEventCreate(&r.a);
+    (void)hipEventCreate(&r.b);
+    (void)hipEventRecord(r.a, st);
+    launch();
+    (void)hipEventRecord(r.b, st);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back(r);
+}
+
+}  // namespace
+
+extern "C" snap_params snap_default_params(void) {
+    snap_params p;
+    p.n_min = 10; p.n_cap = 32; p.bp_per_seed = 100; p.conf_c = 2; p.max_hits = 300; p.d_max_pct = 0; p.bucket = 32;
+    return p;
+}
+
+extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
+
+extern "C" size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t total_bases,
+                                             int32_t max_len, int32_t d_max, const snap_params *p) {
+    if (!ix || n_reads < 0 || total_bases < 0 || max_len < 0 || d_max < 0 || !valid_params(p)) return 0;
+    Rule rule = make_rule(ix, d_max, p);
+    const int NS = seeds_for_length(rule, max_len);
+    const int64_t R = std::max<int64_t>(1, std::min<int64_t>(n_reads, CHUNK_READS));
+    return make_layout(n_reads, total_bases, NS, p->max_hits, R, R * 32).total;
+}
+
+extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
+                          int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,
+                          int32_t *second, int8_t *call, void *workspace, size_t ws_bytes, void *stream) {
+    if (!ix || n_reads < 0 || d_max < 0 || !valid_params(p)) return SNAP_EINVAL;
+    if (n_reads == 0) return SNAP_OK;
+    if (!reads || !lengths || !pos || !strand || !dist || !second || !call || !workspace) return SNAP_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return SNAP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const Rule rule = make_rule(ix, d_max, p);
+    const Shifts sh = make_shifts(ix->d.s);
+
+    // read offsets, total bases and longest read (one wait for two scalars)
+    Layout l0 = make_layout(n_reads, 0, 1, 1, 1, 0);
+    if (ws_bytes < l0.off_probe) return SNAP_ENOMEM;
+    char *ws = (char *)workspace;
+    int64_t *roff = (int64_t *)(ws + l0.off_roff);
+    // misc block sits after the stream arrays, whose size needs B: use the tail of
+    // the workspace for the two scalars until the real layout is known
+    uint64_t *tmp_scalars = (uint64_t *)(ws + ((ws_bytes - 64) & ~(size_t)255));
+    {
+        size_t tb = scan_tmp_bytes(n_reads + 1);
+        size_t scan_at = align256(l0.off_roff + sizeof(int64_t) * (size_t)(n_reads + 1));
+        if (scan_at + tb > ((ws_bytes - 64) & ~(size_t)255)) return SNAP_ENOMEM;
+        CastLen f{lengths, n_reads};
+        HIP_OK(scan_excl(ws + scan_at, tb, f, n_reads + 1, roff, st));
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)tmp_scalars, 2, 0u);
+        hipLaunchKernelGGL(k_maxlen, dim3(256), dim3(256), 0, st, lengths, n_reads, (uint32_t *)tmp_scalars);
+        HIP_OK(hipMemcpyAsync(tmp_scalars + 1, roff + n_reads, 8, hipMemcpyDeviceToDevice, st));
+    }
+    uint64_t host_sc[2];
+    HIP_OK(hipMemcpyAsync(host_sc, tmp_scalars, 16, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const uint32_t maxlen_u = (uint32_t)host_sc[0];
+    const int64_t B = (int64_t)host_sc[1];
+    if (maxlen_u & 0x80000000u) return SNAP_EINVAL;
+    const int maxL = (int)maxlen_u;
+    const int NS = std::max(1, seeds_for_length(rule, maxL));
+    const int Kmax = dmax_for_length(rule, maxL) + rule.c - 1;
+    if (Kmax > VERIFY_KMAX || maxL > VERIFY_LMAX) return SNAP_EINVAL;
+
+    // chunk size and pool from the workspace
+    int64_t R = std::min<int64_t>(n_reads, CHUNK_READS);
+    Layout l = make_layout(n_reads, B, NS, rule.hmax, R, 0);
+    while (l.total > ws_bytes && R > 1) {
+        R = std::max<int64_t>(1, R / 2);
+        l = make_layout(n_reads, B, NS, rule.hmax, R, 0);
+    }
+    if (l.total > ws_bytes) return SNAP_ENOMEM;
+    {
+        int64_t extra = (int64_t)((ws_bytes - l.total) / POOL_SLOT_BYTES);
+        l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots + extra);
+        while (l.total > ws_bytes) l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots - 64);
+    }
+    uint32_t *rcode = (uint32_t *)(ws + l.off_rcode);
+    uint32_t *rmask = (uint32_t *)(ws + l.off_rmask);
+    int64_t *misc = (int64_t *)(ws + l.off_misc);
+    ProbeRec *probe = (ProbeRec *)(ws + l.off_probe);
+    uint32_t *hits = (uint32_t *)(ws + l.off_hits);
+    int64_t *hoff = (int64_t *)(ws + l.off_hoff);
+    uint32_t *ccount = (uint32_t *)(ws + l.off_ccount);
+    int64_t *coff = (int64_t *)(ws + l.off_coff);
+    void *scan_tmp = ws + l.off_scan;
+    const int64_t PS = l.pool_slots;
+    char *pool = ws + l.off_pool;
+    auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
+    uint64_t *key_res = (uint64_t *)carve(8 * (size_t)PS);
+    uint32_t *mask_res = (uint32_t *)carve(4 * (size_t)PS);
+    uint64_t *key_c = (uint64_t *)carve(8 * (size_t)PS);
+    uint32_t *mask_c = (uint32_t *)carve(4 * (size_t)PS);
+    uint32_t *cread = (uint32_t *)carve(4 * (size_t)PS);
+    uint64_t *bmin = (uint64_t *)carve(8 * (size_t)PS);
+    uint8_t *dcap = (uint8_t *)carve((size_t)PS);
+    uint8_t *scored = (uint8_t *)carve((size_t)PS);
+    // the per-location step counts reuse the reserved-key area, which is dead
+    // once the locations are compacted
+    uint32_t *steps = g_prof_on ? (uint32_t *)key_res : nullptr;
+    unsigned long long *steps_sum = (unsigned long long *)(misc + 2);
+    if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
+
+    // pack reads
+    {
+        const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
+        timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk); });
+    }
+    const int RW = (std::max(maxL, 1) + 15) / 16 + 1;
+    const int TW = (std::max(maxL, 1) + Kmax + 15) / 16 + 1;
+    const int kmax_t = Kmax <= 15 ? 15 : (Kmax <= 31 ? 31 : 63);
+    const size_t lds = (size_t)64 * 4 * (2 * RW + 2 * TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
+    {
+        int dev = 0, lds_max = 0;
+        HIP_OK(hipGetDevice(&dev));
+        HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (lds > (size_t)lds_max) return SNAP_EINVAL;
+    }
+
+    for (int64_t r0 = 0; r0 < n_reads;) {
+        int64_t nr = std::min<int64_t>(R, n_reads - r0);
+        ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, r0, nr, NS, rule, sh, probe};
+        const int64_t pthreads = nr * NS * 8;
+        timed("probe", st, [&] { hipLaunchKernelGGL(k_probe, dim3((unsigned)((pthreads + 255) / 256)), dim3(256), 0, st, pa); });
+        timed("hitcount", st, [&] { hipLaunchKernelGGL(k_hitcount, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, probe, nr, NS, hits); });
+        size_t tb = scan_tmp_bytes(nr + 1);
+        HIP_OK(scan_excl(scan_tmp, tb, CastU32{hits, nr}, nr + 1, hoff, st));
+        int64_t total = 0;
+        HIP_OK(hipMemcpyAsync(&total, hoff + nr, 8, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (total > PS) {
+            // keep the longest prefix of reads whose hits fit; the rest go to the next pass
+            hipLaunchKernelGGL(k_fit, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, hoff, nr, PS, misc);
+            int64_t fit = 0;
+            HIP_OK(hipMemcpyAsync(&fit, misc, 8, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (fit <= 0) return SNAP_ENOMEM;
+            nr = fit;
+            HIP_OK(hipMemcpyAsync(&total, hoff + nr, 8, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+        }
+        CandArgs ca{probe, NS, ix->d.positions, ix->d.G, ix->d.s, lengths, r0, nr, hoff, key_res, mask_res, ccount};
+        timed("candidates", st, [&] { hipLaunchKernelGGL(k_candidates, dim3((unsigned)((nr + 127) / 128)), dim3(128), 0, st, ca); });
+        tb = scan_tmp_bytes(nr + 1);
+        HIP_OK(scan_excl(scan_tmp, tb, CastU32{ccount, nr}, nr + 1, coff, st));
+        timed("compact", st, [&] { hipLaunchKernelGGL(k_compact, dim3((unsigned)((nr + 127) / 128)), dim3(128), 0, st, hoff, coff, ccount, nr,
+                           key_res, mask_res, key_c, mask_c, cread); });
+        if (total > 0) {
+            VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, r0, key_c, cread, coff + nr,
+                          rule, RW, TW, dcap, steps};
+            const unsigned vb = (unsigned)((total + 63) / 64);
+            timed("verify", st, [&] {
+                if (kmax_t == 15)
+                    hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), lds, st, va);
+                else if (kmax_t == 31)
+                    hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), lds, st, va);
+                else
+                    hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
+            });
+        }
+        ReplayArgs ra{probe, NS, key_c, mask_c, dcap, coff, ccount, bmin, scored, lengths, r0, nr, rule,
+                      pos, strand, dist, second, call};
+        timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3((unsigned)((nr + 127) / 128)), dim3(128), 0, st, ra); });
+        HIP_OK(hipGetLastError());
+        if (g_prof_on) {
+            // counters for the roofline: one extra wait per pass, profiling only
+            unsigned long long zero = 0, ssum = 0;
+            int64_t ncand = 0;
+            if (total > 0) {
+                HIP_OK(hipMemcpyAsync(steps_sum, &zero, 8, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_sum_u32, dim3(256), dim3(256), 0, st, steps, coff + nr, steps_sum);
+                HIP_OK(hipMemcpyAsync(&ssum, steps_sum, 8, hipMemcpyDeviceToHost, st));
+            }
+            HIP_OK(hipMemcpyAsync(&ncand, coff + nr, 8, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            std::lock_guard<std::mutex> g(g_prof_mu);
+            g_ctr.passes += 1;
+            g_ctr.reads += nr;
+            g_ctr.seed_slots += nr * NS;
+            g_ctr.hits += total;
+            g_ctr.locations += ncand;
+            g_ctr.lv_steps += (int64_t)ssum;
+            g_ctr.bases += 0;
+        }
+        r0 += nr;
+    }
+    return SNAP_OK;
+}
+
+// Seed offsets tried for a read of length L (host evaluation of the same
+// functions the probe kernel uses).
+extern "C" int32_t snap_debug_seed_offsets(int32_t L, int32_t s, int32_t n, int32_t *out) {
+    if (!out || s < 1 || s > 32 || n < 0 || n > 64) return 0;
+    const Shifts sh = make_shifts(s);
+    int32_t k = 0;
+    for (int i = 0; i < n; i++) {
+        int o = seed_offset(sh, s, L, i);
+        if (o < 0) break;
+        out[k++] = o;
+    }
+    return k;
+}
+
+extern "C" int snap_profile_begin(void) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &r : g_prof) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    g_prof.clear();
+    std::memset(&g_ctr, 0, sizeof(g_ctr));
+    g_prof_on = true;
+    return SNAP_OK;
+}
+
+extern "C" int snap_profile_counters(snap_counters *out) {
+    if (!out) return SNAP_EINVAL;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    *out = g_ctr;
+    return SNAP_OK;
+}
+
+extern "C" int snap_profile_end(snap_kernel_time *out, int32_t cap, int32_t *count) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = false;
+    std::vector<std::string> names;
+    std::vector<int64_t> launches;
+    std::vector<double> ms;
+    int rc = SNAP_OK;
+    for (auto &r : g_prof) {
+        float t = 0;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) rc = SNAP_EDEVICE;
+        size_t k = 0;
+        while (k < names.size() && names[k] != r.name) k++;
+        if (k == names.size()) { names.push_back(r.name); launches.push_back(0); ms.push_back(0); }
+        launches[k]++;
+        ms[k] += t;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    int32_t n = 0;
+    for (size_t k = 0; k < names.size() && (int32_t)k < cap; k++, n++) {
+        std::memset(&out[k], 0, sizeof(out[k]));
+        std::strncpy(out[k].name, names[k].c_str(), sizeof(out[k].name) - 1);
+        out[k].launches = launches[k];
+        out[k].total_ms = ms[k];
+    }
+    if (count) *count = n;
+    return rc;
+}
+
+// Plain device copy (one dword per lane per step), used to calibrate hardware
+// byte counters against a transfer of known size.
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+extern "C" int snap_debug_copy(const void *src, void *dst, uint64_t bytes, void *stream) {
+    if (!src || !dst || (bytes & 3)) return SNAP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = (int64_t)(bytes / 4);
+    timed("copy", st, [&] { hipLaunchKernelGGL(k_copy_u32, dim3(4096), dim3(256), 0, st, (const uint32_t *)src, (uint32_t *)dst, n); });
+    return hipGetLastError() == hipSuccess ? SNAP_OK : SNAP_EDEVICE;
+}

@@ -1,0 +1,220 @@
+"""HIP path vs the CPU oracle: bit-exact on all five outputs (pos, strand, dist,
+second, call) for every read, on seeded synthetic workloads with the shapes of
+the paper's (Section 2: uniform and repeat-rich genomes, 100 / 250 bp and longer
+reads, substitutions and indels), plus edge cases and invariance checks.
+All of this is integer work, so the tolerance is zero.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from helpers import compare, gpu_align, oracle_align, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def snapgpu(torch_cuda):
+    import paper_1111_5572_amd as m
+    m.lib()   # fails loudly if the HIP library is missing
+    return m
+
+
+def _world(synth_mod, workload, G, n):
+    w = workload.scaled(genome_len=G, n_reads=n)
+    g = w.make_genome()
+    return w, g, w.make_reads(g)
+
+
+def _check(snapgpu, oracle_mod, w, g, reads, label, params=None, d_max=None, ws=None, gix=None, oix=None):
+    params = params or w.params
+    d_max = params.d_max if d_max is None else d_max
+    say(f"[{label}] G={len(g)} reads={reads.n} d_max={d_max} c={params.conf_c} hmax={params.max_hits}")
+    own_g = gix is None
+    gix = gix or snapgpu.Index(g, params.seed_len)
+    gp = snapgpu.params_from(params)
+    gout = gpu_align(snapgpu, gix, reads, d_max, gp, workspace_bytes=ws)
+    own_o = oix is None
+    oix = oix or oracle_mod.Index(g, params.seed_len)
+    oout = oracle_align(oracle_mod, oix, reads, params)
+    nbad, rep = compare(gout, oout, reads, label)
+    if own_g:
+        gix.close()
+    if own_o:
+        oix.close()
+    assert nbad == 0, rep
+    return gout
+
+
+def test_tiny_full_config(snapgpu, oracle_mod, synth_mod):
+    from synth.workloads import TINY
+    g = TINY.make_genome()
+    reads = TINY.make_reads(g)
+    out = _check(snapgpu, oracle_mod, TINY, g, reads, "tiny")
+    assert (out[4] == 1).mean() > 0.99
+
+
+def test_mid_recipe_scaled(snapgpu, oracle_mod, synth_mod):
+    from synth.workloads import MID
+    w, g, reads = _world(synth_mod, MID, 3_000_000, 30_000)
+    out = _check(snapgpu, oracle_mod, w, g, reads, "mid-scaled")
+    calls = np.bincount(out[4], minlength=3)
+    say(f"  calls not/single/multi = {calls.tolist()}")
+    assert calls[2] > 0   # repeats produce ambiguous reads
+
+
+def test_human_recipe_scaled_with_n(snapgpu, oracle_mod, synth_mod):
+    from synth.workloads import HUMAN
+    w, g, reads = _world(synth_mod, HUMAN, 3_000_000, 20_000)
+    assert (g == ord("N")).mean() > 0.005
+    _check(snapgpu, oracle_mod, w, g, reads, "human-scaled")
+
+
+@pytest.mark.parametrize("c,hmax,dmax", [(1, 300, 10), (3, 300, 10), (2, 8, 10), (2, 60, 4), (2, 300, 0)])
+def test_parameter_sweep(snapgpu, oracle_mod, synth_mod, c, hmax, dmax):
+    from dataclasses import replace
+    from synth.workloads import MID
+    w, g, reads = _world(synth_mod, MID, 1_500_000, 8_000)
+    p = replace(w.params, conf_c=c, max_hits=hmax, d_max=dmax)
+    _check(snapgpu, oracle_mod, w, g, reads, f"sweep c={c} h={hmax} d={dmax}", params=p)
+
+
+def test_long_reads_percent_dmax(snapgpu, oracle_mod, synth_mod):
+    """Reads 100-700 bp with d_max = ceil(0.08 L) and the long-read error model."""
+    from dataclasses import replace
+    from synth.workloads import BATCHED
+    w = BATCHED.scaled(genome_len=2_000_000, n_reads=1500)
+    w = replace(w, reads=replace(w.reads, len_b=700))
+    g = w.make_genome()
+    reads = w.make_reads(g)
+    _check(snapgpu, oracle_mod, w, g, reads, "long-pct")
+
+
+def test_small_workspace_many_passes(snapgpu, oracle_mod, synth_mod):
+    """The minimum workspace forces many internal passes; outputs are unchanged."""
+    from synth.workloads import MID
+    w, g, reads = _world(synth_mod, MID, 1_000_000, 6_000)
+    gix = snapgpu.Index(g, 20)
+    gp = snapgpu.params_from(w.params)
+    full = gpu_align(snapgpu, gix, reads, w.params.d_max, gp)
+    wmin = snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), int(reads.lengths.max()),
+                                   w.params.d_max, gp)
+    # smaller than the recommended size but above the one-read minimum
+    small = gpu_align(snapgpu, gix, reads, w.params.d_max, gp, workspace_bytes=max(wmin // 40, 1 << 20))
+    nbad, rep = compare(small, full, reads, "small workspace vs default")
+    gix.close()
+    assert nbad == 0, rep
+
+
+def test_batch_composition_invariance(snapgpu, synth_mod):
+    """A read's output does not depend on the other reads in the batch or their order."""
+    from synth.workloads import MID
+    w, g, reads = _world(synth_mod, MID, 1_000_000, 5_000)
+    gix = snapgpu.Index(g, 20)
+    gp = snapgpu.params_from(w.params)
+    full = gpu_align(snapgpu, gix, reads, w.params.d_max, gp)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(reads.n)
+    sub = reads.subset(perm)
+    shuf = gpu_align(snapgpu, gix, sub, w.params.d_max, gp)
+    back = tuple(np.empty_like(x) for x in shuf)
+    for b, s in zip(back, shuf):
+        b[perm] = s
+    nbad, rep = compare(back, full, reads, "shuffled vs original")
+    assert nbad == 0, rep
+    few = perm[:37]
+    part = gpu_align(snapgpu, gix, reads.subset(few), w.params.d_max, gp)
+    nbad, rep = compare(part, tuple(x[few] for x in full), None, "subset vs full")
+    gix.close()
+    assert nbad == 0, rep
+
+
+def test_edge_cases(snapgpu, oracle_mod, synth_mod):
+    """Empty batch; reads shorter than s, of length exactly s; N-rich reads; reads at
+    the genome ends; identical reads in one batch."""
+    import torch
+    import synth
+    g = synth_mod.genome_uniform(200_000, 9)
+    gs = g.tobytes().decode()
+    seqs = ["", "ACGT", gs[10:29], gs[10:30], gs[0:100], gs[-100:], "N" * 100,
+            gs[500:550] + "N" + gs[551:600], gs[700:800].lower(), gs[900:1000], gs[900:1000],
+            gs[5000:5250], "ACGTX" * 20]
+    lens = np.array([len(x) for x in seqs], np.int32)
+    offs = np.zeros(len(seqs) + 1, np.int64)
+    np.cumsum(lens, out=offs[1:])
+    bases = np.frombuffer("".join(seqs).encode(), np.uint8).copy()
+    n = len(seqs)
+    reads = synth.Reads(bases, lens, offs, np.zeros(n, np.int64), np.zeros(n, np.int8), np.zeros(n, np.int32))
+    from synth.workloads import TINY
+    gix = snapgpu.Index(g, 20)
+    oix = oracle_mod.Index(g, 20)
+    gp = snapgpu.params_from(TINY.params)
+    gout = gpu_align(snapgpu, gix, reads, 8, gp)
+    oout = oracle_align(oracle_mod, oix, reads, TINY.params)
+    nbad, rep = compare(gout, oout, reads, "edges")
+    assert nbad == 0, rep
+    # empty batch
+    dev = torch.device("cuda:0")
+    empty = snapgpu.align(gix, torch.empty(0, dtype=torch.uint8, device=dev),
+                          torch.empty(0, dtype=torch.int32, device=dev), 8, gp, max_len=0)
+    assert empty.pos.numel() == 0
+    gix.close()
+    oix.close()
+
+
+def test_invalid_arguments(snapgpu, synth_mod):
+    import torch
+    g = synth_mod.genome_uniform(10_000, 1)
+    gix = snapgpu.Index(g, 20)
+    dev = torch.device("cuda:0")
+    rb = torch.zeros(100, dtype=torch.uint8, device=dev)
+    ln = torch.full((1,), 100, dtype=torch.int32, device=dev)
+    with pytest.raises(snapgpu.SnapError):
+        snapgpu.align(gix, rb, ln, -1)
+    with pytest.raises(snapgpu.SnapError):
+        snapgpu.align(gix, rb, ln, 8, snapgpu.default_params(conf_c=0))
+    with pytest.raises(snapgpu.SnapError):
+        snapgpu.align(gix, rb, ln, 8, snapgpu.default_params(n_cap=33))
+    with pytest.raises(snapgpu.SnapError):
+        snapgpu.align(gix, rb, ln, snapgpu.max_limit() + 5)
+    with pytest.raises(snapgpu.SnapError):
+        snapgpu.Index(b"ACGT", 20)
+    gix.close()
+
+
+def test_mid_full_size_sampled(snapgpu, oracle_mod, synth_mod):
+    """The mid workload at full size (100 Mbase, 10M reads) in the launch
+    configuration the benchmark times; the oracle re-computes a seeded sample."""
+    if os.environ.get("SNAP_SKIP_FULL"):
+        pytest.skip("SNAP_SKIP_FULL set")
+    from synth.workloads import MID
+    g = MID.make_genome()
+    say("[mid-full] genome ready")
+    reads = MID.make_reads(g)
+    say("[mid-full] reads ready")
+    gix = snapgpu.Index(g, 20)
+    say("[mid-full] GPU index ready")
+    gp = snapgpu.params_from(MID.params)
+    gout = gpu_align(snapgpu, gix, reads, MID.params.d_max, gp)
+    say("[mid-full] GPU aligned")
+    gix.close()
+    rng = np.random.default_rng(2024)
+    idx = np.sort(rng.choice(reads.n, 3000, replace=False))
+    sub = reads.subset(idx)
+    oix = oracle_mod.Index(g, 20)
+    say("[mid-full] oracle index ready")
+    oout = oracle_align(oracle_mod, oix, sub, MID.params)
+    oix.close()
+    nbad, rep = compare(tuple(x[idx] for x in gout), oout, sub, "mid-full sample")
+    assert nbad == 0, rep
+    calls = np.bincount(gout[4], minlength=3)
+    say(f"  calls not/single/multi = {calls.tolist()}")
