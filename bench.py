@@ -30,9 +30,10 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # Algorithmic bytes / ops per unit, per kernel (the design notes derive them).
 PROBE_BYTES_PER_SLOT = 128 + 32       # one 128-byte bucket line read, one 32-byte probe record written
-CAND_BYTES_PER_SLOT = 32              # probe record read back
-CAND_BYTES_PER_HIT = 4 + 12           # position read, location key + seed mask written
-CAND_BYTES_PER_READ = 4               # location count written
+GATHER_BYTES_PER_SLOT = 32            # probe record read
+GATHER_BYTES_PER_HIT = 4 + 8          # position read, hit record written
+DEDUPE_BYTES_PER_HIT = 8              # hit record read
+DEDUPE_BYTES_PER_LOC = 12             # location key + seed mask written
 VERIFY_OPS_PER_STEP = 30              # integer ops per diagonal extension (neighbour max, bounds, one 16-base compare)
 
 
@@ -123,10 +124,12 @@ def main():
     if dom == "probe":
         bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
         work = ctr["seed_slots"] * PROBE_BYTES_PER_SLOT * per_launch / 1e9
-    elif dom == "candidates":
+    elif dom == "gather":
         bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
-        work = (ctr["seed_slots"] * CAND_BYTES_PER_SLOT + ctr["hits"] * CAND_BYTES_PER_HIT +
-                ctr["reads"] * CAND_BYTES_PER_READ) * per_launch / 1e9
+        work = (ctr["seed_slots"] * GATHER_BYTES_PER_SLOT + ctr["hits"] * GATHER_BYTES_PER_HIT) * per_launch / 1e9
+    elif dom.startswith("dedupe"):
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = (ctr["hits"] * DEDUPE_BYTES_PER_HIT + ctr["locations"] * DEDUPE_BYTES_PER_LOC) * per_launch / 1e9
     elif dom == "verify":
         bound, unit, peak = "alu", "TOP/s", VALU_PEAK_TOPS
         work = ctr["lv_steps"] * VERIFY_OPS_PER_STEP * per_launch / 1e12

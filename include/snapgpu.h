@@ -148,6 +148,26 @@ int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *length
 /* Largest limit d_max(L) + c - 1 the verify kernels accept. */
 int32_t snap_max_limit(void);
 
+/*
+ * Output-invariant schedule of snap_align (process-wide). A first pass probes
+ * only the first pass1_seeds seed slots of every read and verifies locations
+ * with limit pass1_limit; Algorithm 1 is replayed on that, and a read is settled
+ * whenever the replay never needs a seed or a distance beyond what the pass
+ * computed. The reads left over go through a pass with every seed and limit
+ * pass2_limit (when set), and what is still left through a pass with every seed
+ * and the full limit d_max(L) + c - 1. 0 in a field means "no cap" (a single
+ * complete pass when all are 0). Outputs never depend on these values.
+ */
+typedef struct {
+    int32_t pass1_seeds;
+    int32_t pass1_limit;
+    int32_t pass2_limit;
+    int32_t reserved;
+} snap_tuning;
+
+int snap_set_tuning(const snap_tuning *t);
+int snap_get_tuning(snap_tuning *t);
+
 /* ------------------------------------------------------- instrumentation */
 
 /* Device time of one kernel of the path, summed over launches. */
@@ -177,7 +197,7 @@ typedef struct {
     int64_t hits;         /* seed hits gathered (h_max-passing seeds) */
     int64_t locations;    /* distinct (strand, p) locations verified */
     int64_t lv_steps;     /* diagonal extensions run by the verify kernel */
-    int64_t bases;        /* reserved */
+    int64_t second_pass_reads; /* reads a first pass left to the complete pass */
 } snap_counters;
 
 int snap_profile_counters(snap_counters *out);

@@ -44,9 +44,25 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "pass2_limit", "reserved")]
+
+
+def set_tuning(pass1_seeds: int, pass1_limit: int, pass2_limit: int = 0):
+    """Output-invariant pass schedule (see snap_set_tuning); 0 = no cap."""
+    _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, pass2_limit, 0))),
+           "snap_set_tuning")
+
+
+def get_tuning() -> tuple[int, int, int]:
+    t = Tuning()
+    _check(lib().snap_get_tuning(ctypes.byref(t)), "snap_get_tuning")
+    return int(t.pass1_seeds), int(t.pass1_limit), int(t.pass2_limit)
+
+
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "bases")]
+                ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "second_pass_reads")]
 
 
 def lib():
@@ -83,6 +99,10 @@ def lib():
         L.snap_profile_end.restype = ctypes.c_int
         L.snap_profile_counters.argtypes = [ctypes.POINTER(Counters)]
         L.snap_profile_counters.restype = ctypes.c_int
+        L.snap_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.snap_set_tuning.restype = ctypes.c_int
+        L.snap_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.snap_get_tuning.restype = ctypes.c_int
         L.snap_debug_copy.argtypes = [P, P, u64, P]
         L.snap_debug_copy.restype = ctypes.c_int
         _lib = L
@@ -243,7 +263,7 @@ def profile_end() -> dict:
 def profile_counters() -> dict:
     c = Counters()
     _check(lib().snap_profile_counters(ctypes.byref(c)), "snap_profile_counters")
-    return {n: int(getattr(c, n)) for n, _ in c._fields_ if n != "bases"}
+    return {n: int(getattr(c, n)) for n, _ in c._fields_}
 
 
 def debug_copy(src, dst, nbytes: int, stream=None):

@@ -193,13 +193,27 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 
 // ----------------------------------------------------------------- probe
 
+// A pass works on a list of reads: entry r0 + r of `ridx` (or read r0 + r when
+// there is no list) for r in [0, nr).
+struct Pass {
+    const uint32_t *ridx;
+    int64_t r0, nr;
+    int32_t NS;        // seed slots probed in this pass
+    int32_t Kcap;      // verify limit cap: distances above min(Kcap, K(L)) stay unknown
+    int32_t final_pass;
+};
+
+__device__ inline int64_t gid(const Pass &p, int64_t r) {
+    return p.ridx ? (int64_t)p.ridx[p.r0 + r] : p.r0 + r;
+}
+
+
 struct ProbeArgs {
     DevIndex ix;
     const uint32_t *rcode, *rmask;
-    const int64_t *roff;   // global read offsets (bases)
+    const int64_t *roff;   // read offsets (bases) in the packed stream
     const int32_t *len;
-    int64_t r0, nr;        // chunk: reads [r0, r0 + nr)
-    int32_t NS;            // seed slots per read
+    Pass ps;
     Rule rule;
     Shifts sh;
     ProbeRec *out;         // nr * NS records
@@ -213,16 +227,18 @@ __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
     const int sub = (int)(gt & 7);
     const int lane = threadIdx.x & 63;
     const int s = a.ix.s;
-    const bool valid = item < a.nr * (int64_t)a.NS;
-    int64_t r = valid ? item / a.NS : 0;
-    int i = valid ? (int)(item % a.NS) : 0;
-    int L = valid ? a.len[a.r0 + r] : 0;
+    const int NS = a.ps.NS;
+    const bool valid = item < a.ps.nr * (int64_t)NS;
+    const int64_t r = valid ? item / NS : 0;
+    const int i = valid ? (int)(item % NS) : 0;
+    const int64_t g = valid ? gid(a.ps, r) : 0;
+    const int L = valid ? a.len[g] : 0;
     int o = -1;
     if (valid && i < seeds_for_length(a.rule, L)) o = seed_offset(a.sh, s, L, i);
     int status = ST_NONE;
     uint64_t key = 0, canon = 0;
     if (o >= 0) {
-        const int64_t x = STREAM_GUARD + a.roff[a.r0 + r] + o;
+        const int64_t x = STREAM_GUARD + a.roff[g] + o;
         const int64_t w = x >> 4;
         const uint32_t sh = (uint32_t)(x & 15) * 2;
         uint64_t lo = (uint64_t)a.rcode[w] | ((uint64_t)a.rcode[w + 1] << 32);
@@ -305,79 +321,210 @@ __global__ void k_hitcount(const ProbeRec *pr, int64_t nr, int NS, uint32_t *hit
     hits[r] = h;
 }
 
-struct CandArgs {
+constexpr uint64_t HIT_NONE = ~0ull;
+
+struct GatherArgs {
     const ProbeRec *pr;
-    int32_t NS;
     const uint32_t *positions;
     uint64_t G;
     int32_t s;
     const int32_t *len;
-    int64_t r0, nr;
-    const int64_t *hoff;     // reserved region per read
-    uint64_t *key;           // p << 1 | strand, sorted per read
-    uint32_t *mask;          // seeds that voted
-    uint32_t *count;         // distinct locations per read
+    Pass ps;
+    const int64_t *hoff;
+    uint64_t *hk;      // per hit: ((p << 1 | strand) << 5) | seed slot, or HIT_NONE
 };
 
-__device__ inline void cand_insert(uint64_t *key, uint32_t *mask, int64_t base, uint32_t &C, uint64_t k,
-                                   uint32_t bit) {
-    uint32_t lo = 0, hi = C;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (key[base + mid] < k) lo = mid + 1; else hi = mid;
+// Algorithm 1's vote loop, one thread per (read, seed slot): a forward hit q of
+// the seed at offset o votes for (+, q - o), a reverse hit for (-, q - (L - o - s));
+// locations outside [0, G - L] are dropped.
+__global__ void k_gather(GatherArgs a) {
+    const int NS = a.ps.NS;
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= a.ps.nr * NS) return;
+    const int64_t r = item / NS;
+    const int i = (int)(item % NS);
+    const ProbeRec p = a.pr[item];
+    if (p.status != ST_OK || p.nf + p.nr == 0) return;
+    int64_t off = a.hoff[r];
+    for (int i2 = 0; i2 < i; i2++) {
+        const ProbeRec &q = a.pr[r * NS + i2];
+        if (q.status == ST_OK) off += q.nf + q.nr;
     }
-    if (lo < C && key[base + lo] == k) {
-        mask[base + lo] |= bit;
-        return;
+    const int64_t L = a.len[gid(a.ps, r)];
+    for (uint32_t j = 0; j < p.nf; j++) {
+        const int64_t pp = (int64_t)a.positions[p.off_f + j] - p.o;
+        a.hk[off + j] = (pp >= 0 && pp + L <= (int64_t)a.G) ? ((((uint64_t)pp << 1)) << 5) | (uint64_t)i : HIT_NONE;
     }
-    for (uint32_t j = C; j > lo; j--) {
-        key[base + j] = key[base + j - 1];
-        mask[base + j] = mask[base + j - 1];
+    off += p.nf;
+    for (uint32_t j = 0; j < p.nr; j++) {
+        const int64_t pp = (int64_t)a.positions[p.off_r + j] - (L - p.o - a.s);
+        a.hk[off + j] = (pp >= 0 && pp + L <= (int64_t)a.G) ? ((((uint64_t)pp << 1) | 1) << 5) | (uint64_t)i : HIT_NONE;
     }
-    key[base + lo] = k;
-    mask[base + lo] = bit;
-    C++;
 }
 
-// Algorithm 1's vote loop: a forward hit q of the seed at offset o votes for
-// (+, q - o); a reverse hit for (-, q - (L - o - s)); locations outside
-// [0, G - L] are dropped.
-__global__ void k_candidates(CandArgs a) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.nr) return;
-    const int64_t L = a.len[a.r0 + r];
-    const int64_t base = a.hoff[r];
-    uint32_t C = 0;
-    for (int i = 0; i < a.NS; i++) {
-        const ProbeRec p = a.pr[r * a.NS + i];
-        if (p.status != ST_OK) continue;
-        const uint32_t bit = 1u << i;
-        for (uint32_t j = 0; j < p.nf; j++) {
-            int64_t q = a.positions[p.off_f + j];
-            int64_t pp = q - p.o;
-            if (pp >= 0 && pp + L <= (int64_t)a.G) cand_insert(a.key, a.mask, base, C, (uint64_t)pp << 1, bit);
-        }
-        for (uint32_t j = 0; j < p.nr; j++) {
-            int64_t q = a.positions[p.off_r + j];
-            int64_t pp = q - (L - p.o - a.s);
-            if (pp >= 0 && pp + L <= (int64_t)a.G) cand_insert(a.key, a.mask, base, C, ((uint64_t)pp << 1) | 1, bit);
-        }
-    }
-    a.count[r] = C;
+struct DedupeArgs {
+    const uint64_t *hk;
+    const uint32_t *hits;
+    const int64_t *hoff;
+    int64_t nr;
+    uint64_t *key;     // distinct locations (p << 1 | strand), ascending, at hoff[r]
+    uint32_t *mask;    // the seed slots that voted for each
+    uint32_t *count;
+    uint32_t *slot_read;   // chunk read of every reserved slot
+};
+
+__device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
+    const uint32_t lo = __shfl_xor((unsigned)(uint32_t)v, m, 64);
+    const uint32_t hi = __shfl_xor((unsigned)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t shfl_up64(uint64_t v, int d) {
+    const uint32_t lo = __shfl_up((unsigned)(uint32_t)v, d, 64);
+    const uint32_t hi = __shfl_up((unsigned)(uint32_t)(v >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t shfl_down64(uint64_t v, int d) {
+    const uint32_t lo = __shfl_down((unsigned)(uint32_t)v, d, 64);
+    const uint32_t hi = __shfl_down((unsigned)(uint32_t)(v >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-__global__ void k_compact(const int64_t *hoff, const int64_t *coff, const uint32_t *count, int64_t nr,
-                          const uint64_t *key_in, const uint32_t *mask_in, uint64_t *key_out, uint32_t *mask_out,
-                          uint32_t *cread) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    const int64_t src = hoff[r], dst = coff[r];
-    const uint32_t C = count[r];
-    for (uint32_t k = 0; k < C; k++) {
-        key_out[dst + k] = key_in[src + k];
-        mask_out[dst + k] = mask_in[src + k];
-        cread[dst + k] = (uint32_t)r;
+// Reads with at most 64 hits: one wave per read, one hit per lane, a 64-lane
+// bitonic sort in registers, then equal locations merged (their seed bits OR-ed)
+// and written in ascending order.
+__global__ __launch_bounds__(256) void k_dedupe_light(DedupeArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < a.nr; r += nwaves) {
+        const uint32_t H = a.hits[r];
+        if (H > 64) continue;
+        const int64_t base = a.hoff[r];
+        if (H == 0) {
+            if (lane == 0) a.count[r] = 0;
+            continue;
+        }
+        uint64_t v = (uint32_t)lane < H ? a.hk[base + lane] : HIT_NONE;
+        for (int k = 2; k <= 64; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const uint64_t o = shfl_xor64(v, j);
+                const bool up = (lane & k) == 0;
+                const bool lower = (lane & j) == 0;
+                const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
+                v = (lower == up) ? mn : mx;
+            }
+        const bool valid = v != HIT_NONE;
+        const uint64_t loc = v >> 5;
+        const uint64_t prev = shfl_up64(loc, 1);
+        const bool first = valid && (lane == 0 || prev != loc);
+        uint32_t acc = valid ? (1u << (v & 31)) : 0u;
+        for (int d = 1; d < 32; d <<= 1) {
+            const uint32_t nb = __shfl_down(acc, d, 64);
+            const uint64_t nloc = shfl_down64(loc, d);
+            if (lane + d < 64 && nloc == loc) acc |= nb;
+        }
+        const uint64_t fb = __ballot(first);
+        const int rank = __popcll(fb & ((1ull << lane) - 1));
+        if (first) {
+            a.key[base + rank] = loc;
+            a.mask[base + rank] = acc;
+        }
+        if ((uint32_t)lane < H) a.slot_read[base + lane] = (uint32_t)r;
+        if (lane == 0) a.count[r] = (uint32_t)__popcll(fb);
     }
+}
+
+// Reads with more than 64 hits: one 256-thread workgroup per read, bitonic sort
+// of the hits in LDS (ascending network with the padding beyond H left in
+// place), then the same merge of equal locations, 256 hits at a time.
+// Reads with more hits than fit in LDS sort in place in a global scratch region
+// of their own (the same code with IN_LDS false).
+template <bool IN_LDS>
+__global__ __launch_bounds__(256) void k_dedupe_heavy(DedupeArgs a, uint64_t *gscratch, uint32_t cape) {
+    extern __shared__ uint64_t lds_keys[];
+    __shared__ uint32_t wcnt[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int64_t r = blockIdx.x; r < a.nr; r += gridDim.x) {
+        const uint32_t H = a.hits[r];
+        if (H <= 64 || (IN_LDS ? H > cape : H <= cape)) continue;
+        const int64_t base = a.hoff[r];
+        uint64_t *sk = IN_LDS ? lds_keys : gscratch + base;
+        uint32_t N = 1;
+        while (N < H) N <<= 1;
+        for (uint32_t i = tid; i < H; i += 256) {
+            sk[i] = a.hk[base + i];
+            a.slot_read[base + i] = (uint32_t)r;
+        }
+        __syncthreads();
+        for (uint32_t k = 2; k <= N; k <<= 1) {
+            const uint32_t half = k >> 1;
+            for (uint32_t i = tid; i < N / 2; i += 256) {
+                const uint32_t blk = i / half, off = i % half;
+                const uint32_t lo = blk * k + off, hi = blk * k + k - 1 - off;
+                if (hi < H) {
+                    const uint64_t x = sk[lo], y = sk[hi];
+                    if (y < x) { sk[lo] = y; sk[hi] = x; }
+                }
+            }
+            __syncthreads();
+            for (uint32_t j = k >> 2; j > 0; j >>= 1) {
+                for (uint32_t i = tid; i < N / 2; i += 256) {
+                    const uint32_t lo = (i / j) * 2 * j + (i % j), hi = lo + j;
+                    if (hi < H) {
+                        const uint64_t x = sk[lo], y = sk[hi];
+                        if (y < x) { sk[lo] = y; sk[hi] = x; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        uint32_t run = 0;
+        for (uint32_t c0 = 0; c0 < H; c0 += 256) {
+            const uint32_t i = c0 + tid;
+            bool first = false;
+            uint32_t acc = 0;
+            uint64_t loc = 0;
+            if (i < H && sk[i] != HIT_NONE) {
+                loc = sk[i] >> 5;
+                first = (i == 0) || ((sk[i - 1] >> 5) != loc);
+                if (first)
+                    for (uint32_t j = i; j < H && (sk[j] >> 5) == loc; j++) acc |= 1u << (sk[j] & 31);
+            }
+            const uint64_t fb = __ballot(first);
+            if (lane == 0) wcnt[w] = (uint32_t)__popcll(fb);
+            __syncthreads();
+            uint32_t before = run, tot = 0;
+            for (int q = 0; q < 4; q++) {
+                if (q < w) before += wcnt[q];
+                tot += wcnt[q];
+            }
+            if (first) {
+                const uint32_t rank = before + (uint32_t)__popcll(fb & ((1ull << lane) - 1));
+                a.key[base + rank] = loc;
+                a.mask[base + rank] = acc;
+            }
+            run += tot;
+            __syncthreads();
+        }
+        if (tid == 0) a.count[r] = run;
+        __syncthreads();
+    }
+}
+
+// One thread per reserved slot: slot j of read r holds location j - hoff[r],
+// kept if that is below the read's count, at coff[r] + (j - hoff[r]).
+__global__ void k_compact(const int64_t *hoff, const int64_t *coff, const uint32_t *count, const uint32_t *slot_read,
+                          int64_t total, const uint64_t *key_in, const uint32_t *mask_in, uint64_t *key_out,
+                          uint32_t *mask_out, uint32_t *cread) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    const uint32_t r = slot_read[j];
+    const int64_t jj = j - hoff[r];
+    if (jj >= (int64_t)count[r]) return;
+    const int64_t dst = coff[r] + jj;
+    key_out[dst] = key_in[j];
+    mask_out[dst] = mask_in[j];
+    cread[dst] = r;
 }
 
 // ----------------------------------------------------------------- verify
@@ -388,7 +535,7 @@ struct VerifyArgs {
     const uint32_t *rcode, *rmask;
     const int64_t *roff;
     const int32_t *len;
-    int64_t r0;
+    Pass ps;
     const uint64_t *key;
     const uint32_t *cread;
     const int64_t *ncand_ptr;   // number of locations (device scalar)
@@ -458,10 +605,10 @@ __global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
     const uint64_t key = a.key[k];
     const int64_t p = (int64_t)(key >> 1);
     const int strand = (int)(key & 1);
-    const int64_t r = a.cread[k];
-    const int L = a.len[a.r0 + r];
-    const int K = dmax_for_length(a.rule, L) + a.rule.c - 1;
-    const int64_t xb = STREAM_GUARD + a.roff[a.r0 + r];
+    const int64_t g = gid(a.ps, a.cread[k]);
+    const int L = a.len[g];
+    const int K = min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
+    const int64_t xb = STREAM_GUARD + a.roff[g];
     const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
 
     const int nrw = (L + 15) >> 4;
@@ -542,7 +689,6 @@ __global__ void k_sum_u32(const uint32_t *v, const int64_t *n_ptr, unsigned long
 
 struct ReplayArgs {
     const ProbeRec *pr;
-    int32_t NS;
     const uint64_t *key;
     const uint32_t *mask;
     const uint8_t *dcap;
@@ -551,14 +697,19 @@ struct ReplayArgs {
     uint64_t *bmin;
     uint8_t *scored;
     const int32_t *len;
-    int64_t r0, nr;
+    Pass ps;
     Rule rule;
+    Shifts sh;
+    uint32_t *pending;          // reads this pass could not settle
+    unsigned long long *npending;
     int64_t *pos;
     int8_t *strand;
     int32_t *dist, *second;
     int8_t *call;
 };
 
+// The best / second-best state of Algorithm 1 with the bucket merge (Section 3.2,
+// omitted aspect 1). Held identically by every lane of the read's wave.
 struct ReadState {
     int d_best, d_second;
     int64_t best_p;
@@ -570,29 +721,42 @@ __device__ inline bool lex_less(int d1, int64_t p1, int s1, int d2, int64_t p2, 
     return d1 < d2 || (d1 == d2 && (p1 < p2 || (p1 == p2 && s1 < s2)));
 }
 
-// Score location k (Algorithm 1's EditDistance call, from its capped distance)
-// and merge the result into its bucket (Section 3.2, omitted aspect 1).
-__device__ inline void replay_score(const ReplayArgs &a, int64_t base, int64_t k, int dmax, ReadState &st) {
-    const int c = a.rule.c;
-    int lim;
-    if (st.d_best > dmax) lim = dmax + c - 1;
-    else if (st.d_second >= st.d_best + c) lim = st.d_best + c - 1;
-    else lim = st.d_best - 1;
-    const int dc = a.dcap[base + k];
-    a.scored[base + k] = 1;
-    if (dc > lim) return;   // the special value: scored, never wins
+// Algorithm 1's three-case d_limit.
+__device__ inline int d_limit(const ReadState &st, int dmax, int c) {
+    if (st.d_best > dmax) return dmax + c - 1;
+    if (st.d_second >= st.d_best + c) return st.d_best + c - 1;
+    return st.d_best - 1;
+}
+
+// A result d <= limit at location k: merge into its bucket and update the state.
+// The bucket representative is the first location of the same strand and bucket
+// in key order; a bucket spans at most 2 * bucket locations, so with a 32-base
+// bucket it is found among the 64 keys ending at k.
+__device__ inline void wave_record(const ReplayArgs &a, int64_t base, int64_t k, int d, ReadState &st, int lane) {
     const uint64_t kk = a.key[base + k];
     const int64_t p = (int64_t)(kk >> 1);
     const int s = (int)(kk & 1);
     const int64_t bk = p / a.rule.bucket;
-    // bucket representative: first location of the same strand in the bucket
     int64_t j = k;
-    while (j > 0 && (int64_t)(a.key[base + j - 1] >> 1) / a.rule.bucket == bk) j--;
-    while (j < k && (int)(a.key[base + j] & 1) != s) j++;
-    const uint64_t nv0 = ((uint64_t)dc << 32) | (uint64_t)p;
+    for (int64_t lo = k; ; lo -= 64) {
+        const int64_t q = lo - lane;
+        bool same = false;
+        if (q >= 0) {
+            const uint64_t kq = a.key[base + q];
+            same = (int64_t)(kq >> 1) / a.rule.bucket == bk && (int)(kq & 1) == s;
+        }
+        const uint64_t m = __ballot(same);
+        // keys are sorted, so the bucket's locations are contiguous: the highest
+        // set lane is its first location in this window
+        if (m) j = lo - (63 - __clzll(m));
+        // the run continues below this window only if every lane matched in bucket
+        const bool inb = (q >= 0) && (int64_t)(a.key[base + q] >> 1) / a.rule.bucket == bk;
+        if (__ballot(inb) != ~0ull || lo - 64 < 0) break;
+    }
+    const uint64_t nv0 = ((uint64_t)d << 32) | (uint64_t)p;
     const uint64_t old = a.bmin[base + j];
     const uint64_t nv = nv0 < old ? nv0 : old;
-    a.bmin[base + j] = nv;
+    if (lane == 0) a.bmin[base + j] = nv;
     const int vd = (int)(nv >> 32);
     const int64_t vp = (int64_t)(nv & 0xFFFFFFFFull);
     if (st.best_rep == j) {
@@ -609,65 +773,125 @@ __device__ inline void replay_score(const ReplayArgs &a, int64_t base, int64_t k
     }
 }
 
-__global__ void k_replay(ReplayArgs a) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.nr) return;
-    const int L = a.len[a.r0 + r];
-    const int dmax = dmax_for_length(a.rule, L), c = a.rule.c;
-    const int64_t base = a.coff[r];
-    const uint32_t C = a.count[r];
-    for (uint32_t k = 0; k < C; k++) {
-        a.scored[base + k] = 0;
-        a.bmin[base + k] = ~0ull;
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = shfl_xor64(v, d);
+        v = o > v ? o : v;
     }
-    ReadState st{DINF, DINF, -1, -1, -1};
-    const int round0 = L / a.rule.s;
-    int t = 0, call = -1;
-    bool looked = false, all_over = true;
-    uint32_t prefix = 0;
-    for (int i = 0; i < a.NS && call < 0; i++) {
-        const int status = a.pr[r * a.NS + i].status;
-        if (status == ST_NONE) break;
-        if (status == ST_N) continue;
-        looked = true;
-        if (status == ST_OVER) continue;
-        all_over = false;
-        prefix |= 1u << i;
-        if (i < round0) t++;
-        // the unscored location with the most seeds hitting; ties to smaller p, then +
-        int64_t kb = -1;
-        int bc = 0;
-        for (uint32_t k = 0; k < C; k++) {
-            const uint32_t m = a.mask[base + k] & prefix;
-            if (!m || a.scored[base + k]) continue;
-            const int cnt = __builtin_popcount(m);
-            if (cnt > bc) { bc = cnt; kb = k; }
+    return v;
+}
+
+// Algorithm 1's control flow over the seed masks and capped distances of one read,
+// one wave per read. EditDistance(Read, Reference[p], d_limit) is answered from
+// the capped distance dc = min(D, Kv + 1): D if dc <= d_limit, the special value if
+// dc > d_limit and d_limit <= Kv; with dc = Kv + 1 < d_limit + 1 the pass lacks
+// the answer and leaves the read to the next pass. The phase that scores every
+// remaining location only changes state at locations whose call returns a
+// distance, so it scans for the next such location in selection order (vote count
+// descending, then p, then strand) instead of visiting each one.
+__global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < a.ps.nr; r += nwaves) {
+        const int64_t g = gid(a.ps, r);
+        const int L = a.len[g];
+        const int dmax = dmax_for_length(a.rule, L), c = a.rule.c;
+        const int Kv = min(dmax + c - 1, a.ps.Kcap);
+        const int NS = a.ps.NS;
+        const int64_t base = a.coff[r];
+        const int64_t C = a.count[r];
+        for (int64_t k = lane; k < C; k += 64) {
+            a.scored[base + k] = 0;
+            a.bmin[base + k] = ~0ull;
         }
-        if (kb >= 0) replay_score(a, base, kb, dmax, st);
-        if (st.d_best < c && st.d_second < st.d_best + c) {
-            call = SNAP_MULTIPLE;
-        } else if (st.d_best < DINF && t >= st.d_best + c) {
-            // score the remaining locations in selection order (counts are frozen)
-            for (int cnt = __builtin_popcount(prefix); cnt >= 1; cnt--)
-                for (uint32_t k = 0; k < C; k++) {
-                    if (a.scored[base + k]) continue;
-                    if (__builtin_popcount(a.mask[base + k] & prefix) == cnt) replay_score(a, base, k, dmax, st);
+        ReadState st{DINF, DINF, -1, -1, -1};
+        const int round0 = L / a.rule.s;
+        int t = 0, call = -1;
+        bool looked = false, all_over = true, ended = false, unresolved = false;
+        uint32_t prefix = 0;
+        for (int i = 0; i < NS; i++) {
+            const int status = a.pr[r * NS + i].status;
+            if (status == ST_NONE) { ended = true; break; }
+            if (status == ST_N) continue;
+            looked = true;
+            if (status == ST_OVER) continue;
+            all_over = false;
+            prefix |= 1u << i;
+            if (i < round0) t++;
+            // the unscored location with the most seeds hitting; ties to smaller p, then +
+            unsigned long long best = 0;
+            for (int64_t k = lane; k < C; k += 64) {
+                const uint32_t m = a.mask[base + k] & prefix;
+                if (!m || a.scored[base + k]) continue;
+                const unsigned long long v = ((unsigned long long)__builtin_popcount(m) << 32) |
+                                             (unsigned long long)(0xFFFFFFFFu - (uint32_t)k);
+                best = v > best ? v : best;
+            }
+            best = wave_max_u64(best);
+            if (best) {
+                const int64_t kb = (int64_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+                const int lim = d_limit(st, dmax, c);
+                const int dc = a.dcap[base + kb];
+                if (dc > Kv && lim > Kv) { unresolved = true; break; }
+                if (lane == 0) a.scored[base + kb] = 1;
+                if (dc <= lim) wave_record(a, base, kb, dc, st, lane);
+            }
+            if (st.d_best < c && st.d_second < st.d_best + c) {
+                call = SNAP_MULTIPLE;
+                ended = true;
+                break;
+            }
+            if (st.d_best < DINF && t >= st.d_best + c) {
+                // score every remaining location; vote counts are frozen now
+                for (int lev = __builtin_popcount(prefix); lev >= 1 && !unresolved; lev--) {
+                    for (int64_t c0 = 0; c0 < C && !unresolved; c0 += 64) {
+                        const int64_t k = c0 + lane;
+                        bool in = false;
+                        int dc = 0;
+                        if (k < C && !a.scored[base + k] && __builtin_popcount(a.mask[base + k] & prefix) == lev) {
+                            in = true;
+                            dc = a.dcap[base + k];
+                        }
+                        for (;;) {
+                            const int lim = d_limit(st, dmax, c);
+                            const bool un = in && dc > Kv && lim > Kv;
+                            const bool ev = in && dc <= lim;
+                            const uint64_t bits = __ballot(un || ev);
+                            if (!bits) break;
+                            const int j = __builtin_ctzll(bits);
+                            if ((__ballot(un) >> j) & 1) { unresolved = true; break; }
+                            const int dj = __shfl(dc, j, 64);
+                            wave_record(a, base, c0 + j, dj, st, lane);
+                            if (lane <= j) in = false;
+                        }
+                    }
                 }
-            break;
+                ended = true;
+                break;
+            }
+        }
+        // all slots of this pass used and the read still has seeds to try
+        if (!ended && !unresolved && NS < seeds_for_length(a.rule, L) && seed_offset(a.sh, a.rule.s, L, NS) >= 0)
+            unresolved = true;
+        if (unresolved && !a.ps.final_pass) {
+            if (lane == 0) a.pending[atomicAdd(a.npending, 1ull)] = (uint32_t)g;
+            continue;
+        }
+        if (call < 0) {
+            if (st.d_best <= dmax && st.d_second >= st.d_best + c) call = SNAP_SINGLE;
+            else if (st.d_best <= dmax || (looked && all_over)) call = SNAP_MULTIPLE;
+            else call = SNAP_NOT_FOUND;
+        }
+        if (lane == 0) {
+            const bool has = st.d_best < DINF;
+            a.pos[g] = has ? st.best_p : -1;
+            a.strand[g] = (int8_t)(has ? st.best_s : -1);
+            a.dist[g] = has ? st.d_best : -1;
+            a.second[g] = st.d_second < DINF ? st.d_second : -1;
+            a.call[g] = (int8_t)call;
         }
     }
-    if (call < 0) {
-        if (st.d_best <= dmax && st.d_second >= st.d_best + c) call = SNAP_SINGLE;
-        else if (st.d_best <= dmax || (looked && all_over)) call = SNAP_MULTIPLE;
-        else call = SNAP_NOT_FOUND;
-    }
-    const int64_t g = a.r0 + r;
-    const bool has = st.d_best < DINF;
-    a.pos[g] = has ? st.best_p : -1;
-    a.strand[g] = (int8_t)(has ? st.best_s : -1);
-    a.dist[g] = has ? st.d_best : -1;
-    a.second[g] = st.d_second < DINF ? st.d_second : -1;
-    a.call[g] = (int8_t)call;
 }
 
 // For each read in the chunk, the largest prefix [0, k) whose reserved region fits.
@@ -701,21 +925,23 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     // batch part
-    size_t off_roff, off_rcode, off_rmask, off_misc;
+    size_t off_roff, off_rcode, off_rmask, off_misc, off_pending;
     // chunk part
-    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan;
-    size_t off_pool;
+    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan, off_pool;
     int64_t R;             // reads per chunk
-    int64_t pool_slots;    // reserved location slots per chunk
+    int64_t pool_slots;    // hit / location slots per chunk
     size_t total;
 };
 
-constexpr size_t POOL_SLOT_BYTES = 8 + 4 + 8 + 4 + 4 + 1 + 8 + 1;   // see the carve list in snap_align
+// pool arrays per slot: hit 8, location key 8 + mask 4 + slot read 4 (by read),
+// compacted key 8 + mask 4 + read 4, bucket minimum 8, capped distance 1, scored flag 1
+constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 1 + 1;
+constexpr int POOL_ARRAYS = 10;
 
 size_t scan_tmp_bytes(int64_t items) {
     size_t b = 0;
     CastLen f{nullptr, 0};
-    scan_excl(nullptr, b, f, items, nullptr, 0);
+    (void)scan_excl(nullptr, b, f, items, nullptr, 0);
     return b;
 }
 
@@ -727,6 +953,7 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     l.off_rcode = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)nblk);
     l.off_rmask = o; o = align256(o + sizeof(uint32_t) * (size_t)nblk);
     l.off_misc = o; o = align256(o + 64);
+    l.off_pending = o; o = align256(o + 2 * sizeof(uint32_t) * (size_t)n);
     l.R = R;
     l.off_probe = o; o = align256(o + sizeof(ProbeRec) * (size_t)R * NS);
     l.off_hits = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
@@ -734,10 +961,10 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     l.off_ccount = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
     l.off_coff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
     l.off_scan = o; o = align256(o + std::max(scan_tmp_bytes(R + 1), scan_tmp_bytes(n + 1)));
-    int64_t minslots = (int64_t)NS * hmax;
+    const int64_t minslots = (int64_t)NS * hmax;
     if (pool_slots < minslots) pool_slots = minslots;
     l.pool_slots = pool_slots;
-    l.off_pool = o; o = align256(o + POOL_SLOT_BYTES * (size_t)pool_slots + 8 * 256);
+    l.off_pool = o; o = align256(o + POOL_SLOT_BYTES * (size_t)pool_slots + POOL_ARRAYS * 256);
     l.total = o;
     return l;
 }
@@ -778,6 +1005,14 @@ void timed(const char *name, hipStream_t st, Launch launch) {
     g_prof.push_back(r);
 }
 
+// Output-invariant schedule of the passes: the first pass probes pass1_seeds seed
+// slots and verifies with limit pass1_limit; reads it cannot settle go to a
+// complete second pass.
+std::mutex g_tune_mu;
+snap_tuning g_tune = {4, 4, 0, 0};   // seeds and limit of stage 1, limit of stage 2
+
+constexpr int KCAP_NONE = 1 << 20;
+
 }  // namespace
 
 extern "C" snap_params snap_default_params(void) {
@@ -788,13 +1023,27 @@ extern "C" snap_params snap_default_params(void) {
 
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
+extern "C" int snap_set_tuning(const snap_tuning *t) {
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0) return SNAP_EINVAL;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune = *t;
+    return SNAP_OK;
+}
+
+extern "C" int snap_get_tuning(snap_tuning *t) {
+    if (!t) return SNAP_EINVAL;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    *t = g_tune;
+    return SNAP_OK;
+}
+
 extern "C" size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t total_bases,
                                              int32_t max_len, int32_t d_max, const snap_params *p) {
     if (!ix || n_reads < 0 || total_bases < 0 || max_len < 0 || d_max < 0 || !valid_params(p)) return 0;
     Rule rule = make_rule(ix, d_max, p);
     const int NS = seeds_for_length(rule, max_len);
     const int64_t R = std::max<int64_t>(1, std::min<int64_t>(n_reads, CHUNK_READS));
-    return make_layout(n_reads, total_bases, NS, p->max_hits, R, R * 32).total;
+    return make_layout(n_reads, total_bases, NS, p->max_hits, R, R * 24).total;
 }
 
 extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
@@ -803,18 +1052,28 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     if (!ix || n_reads < 0 || d_max < 0 || !valid_params(p)) return SNAP_EINVAL;
     if (n_reads == 0) return SNAP_OK;
     if (!reads || !lengths || !pos || !strand || !dist || !second || !call || !workspace) return SNAP_EINVAL;
-    if (((uintptr_t)workspace & 255) != 0) return SNAP_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0 || n_reads >= (1ll << 32)) return SNAP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const Rule rule = make_rule(ix, d_max, p);
     const Shifts sh = make_shifts(ix->d.s);
+    snap_tuning tune;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tune = g_tune;
+    }
+    int dev = 0, lds_max = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // hits that one workgroup can sort in LDS
+    uint32_t cape = 64;
+    while ((size_t)cape * 2 * 8 + 1024 <= (size_t)lds_max) cape *= 2;
 
     // read offsets, total bases and longest read (one wait for two scalars)
     Layout l0 = make_layout(n_reads, 0, 1, 1, 1, 0);
-    if (ws_bytes < l0.off_probe) return SNAP_ENOMEM;
+    if (ws_bytes < l0.off_probe + 4096) return SNAP_ENOMEM;
     char *ws = (char *)workspace;
     int64_t *roff = (int64_t *)(ws + l0.off_roff);
-    // misc block sits after the stream arrays, whose size needs B: use the tail of
-    // the workspace for the two scalars until the real layout is known
+    // until the layout is known (it needs the total), two scalars live at the tail
     uint64_t *tmp_scalars = (uint64_t *)(ws + ((ws_bytes - 64) & ~(size_t)255));
     {
         size_t tb = scan_tmp_bytes(n_reads + 1);
@@ -853,6 +1112,11 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     uint32_t *rcode = (uint32_t *)(ws + l.off_rcode);
     uint32_t *rmask = (uint32_t *)(ws + l.off_rmask);
     int64_t *misc = (int64_t *)(ws + l.off_misc);
+    unsigned long long *npending = (unsigned long long *)(misc + 4);   // two counters
+    unsigned long long *steps_sum = (unsigned long long *)(misc + 6);
+    uint32_t *pending_out = nullptr;
+    unsigned long long *npending_out = nullptr;
+    uint32_t *pending = (uint32_t *)(ws + l.off_pending);
     ProbeRec *probe = (ProbeRec *)(ws + l.off_probe);
     uint32_t *hits = (uint32_t *)(ws + l.off_hits);
     int64_t *hoff = (int64_t *)(ws + l.off_hoff);
@@ -862,102 +1126,164 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     const int64_t PS = l.pool_slots;
     char *pool = ws + l.off_pool;
     auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
+    uint64_t *hk = (uint64_t *)carve(8 * (size_t)PS);
     uint64_t *key_res = (uint64_t *)carve(8 * (size_t)PS);
     uint32_t *mask_res = (uint32_t *)carve(4 * (size_t)PS);
+    uint32_t *slot_read = (uint32_t *)carve(4 * (size_t)PS);
     uint64_t *key_c = (uint64_t *)carve(8 * (size_t)PS);
     uint32_t *mask_c = (uint32_t *)carve(4 * (size_t)PS);
     uint32_t *cread = (uint32_t *)carve(4 * (size_t)PS);
     uint64_t *bmin = (uint64_t *)carve(8 * (size_t)PS);
     uint8_t *dcap = (uint8_t *)carve((size_t)PS);
     uint8_t *scored = (uint8_t *)carve((size_t)PS);
-    // the per-location step counts reuse the reserved-key area, which is dead
-    // once the locations are compacted
-    uint32_t *steps = g_prof_on ? (uint32_t *)key_res : nullptr;
-    unsigned long long *steps_sum = (unsigned long long *)(misc + 2);
     if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
+    // per-location step counts reuse the hit array, dead once locations are compacted
+    uint32_t *steps = g_prof_on ? (uint32_t *)hk : nullptr;
 
-    // pack reads
     {
         const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
         timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk); });
     }
     const int RW = (std::max(maxL, 1) + 15) / 16 + 1;
-    const int TW = (std::max(maxL, 1) + Kmax + 15) / 16 + 1;
-    const int kmax_t = Kmax <= 15 ? 15 : (Kmax <= 31 ? 31 : 63);
-    const size_t lds = (size_t)64 * 4 * (2 * RW + 2 * TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
-    {
-        int dev = 0, lds_max = 0;
-        HIP_OK(hipGetDevice(&dev));
-        HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        if (lds > (size_t)lds_max) return SNAP_EINVAL;
-    }
 
-    for (int64_t r0 = 0; r0 < n_reads;) {
-        int64_t nr = std::min<int64_t>(R, n_reads - r0);
-        ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, r0, nr, NS, rule, sh, probe};
-        const int64_t pthreads = nr * NS * 8;
-        timed("probe", st, [&] { hipLaunchKernelGGL(k_probe, dim3((unsigned)((pthreads + 255) / 256)), dim3(256), 0, st, pa); });
-        timed("hitcount", st, [&] { hipLaunchKernelGGL(k_hitcount, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, probe, nr, NS, hits); });
-        size_t tb = scan_tmp_bytes(nr + 1);
-        HIP_OK(scan_excl(scan_tmp, tb, CastU32{hits, nr}, nr + 1, hoff, st));
-        int64_t total = 0;
-        HIP_OK(hipMemcpyAsync(&total, hoff + nr, 8, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        if (total > PS) {
-            // keep the longest prefix of reads whose hits fit; the rest go to the next pass
-            hipLaunchKernelGGL(k_fit, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, hoff, nr, PS, misc);
-            int64_t fit = 0;
-            HIP_OK(hipMemcpyAsync(&fit, misc, 8, hipMemcpyDeviceToHost, st));
+    // one pass over a list of reads (all reads, or the ones an earlier pass left)
+    auto run_pass = [&](const uint32_t *ridx, int64_t list_len, int NSp, int Kcap, int final_pass) -> int {
+        const int Kp = std::min(Kmax, Kcap);
+        const int TW = (std::max(maxL, 1) + Kp + 15) / 16 + 1;
+        const int kmax_t = Kp <= 15 ? 15 : (Kp <= 31 ? 31 : 63);
+        const size_t lds = (size_t)64 * 4 * (2 * RW + 2 * TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
+        if (lds > (size_t)lds_max) return SNAP_EINVAL;
+        for (int64_t r0 = 0; r0 < list_len;) {
+            int64_t nr = std::min<int64_t>(R, list_len - r0);
+            Pass ps{ridx, r0, nr, NSp, Kcap, final_pass};
+            ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, ps, rule, sh, probe};
+            const int64_t pthreads = nr * NSp * 8;
+            timed("probe", st, [&] { hipLaunchKernelGGL(k_probe, dim3((unsigned)((pthreads + 255) / 256)), dim3(256), 0, st, pa); });
+            timed("hitcount", st, [&] { hipLaunchKernelGGL(k_hitcount, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, probe, nr, NSp, hits); });
+            size_t tb = scan_tmp_bytes(nr + 1);
+            HIP_OK(scan_excl(scan_tmp, tb, CastU32{hits, nr}, nr + 1, hoff, st));
+            // total hits and the largest per-read count (one wait per chunk)
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)misc, 2, 0u);
+            hipLaunchKernelGGL(k_maxlen, dim3(256), dim3(256), 0, st, (const int32_t *)hits, nr, (uint32_t *)misc);
+            HIP_OK(hipMemcpyAsync(misc + 1, hoff + nr, 8, hipMemcpyDeviceToDevice, st));
+            int64_t sc[2];
+            HIP_OK(hipMemcpyAsync(sc, misc, 16, hipMemcpyDeviceToHost, st));
             HIP_OK(hipStreamSynchronize(st));
-            if (fit <= 0) return SNAP_ENOMEM;
-            nr = fit;
-            HIP_OK(hipMemcpyAsync(&total, hoff + nr, 8, hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
-        }
-        CandArgs ca{probe, NS, ix->d.positions, ix->d.G, ix->d.s, lengths, r0, nr, hoff, key_res, mask_res, ccount};
-        timed("candidates", st, [&] { hipLaunchKernelGGL(k_candidates, dim3((unsigned)((nr + 127) / 128)), dim3(128), 0, st, ca); });
-        tb = scan_tmp_bytes(nr + 1);
-        HIP_OK(scan_excl(scan_tmp, tb, CastU32{ccount, nr}, nr + 1, coff, st));
-        timed("compact", st, [&] { hipLaunchKernelGGL(k_compact, dim3((unsigned)((nr + 127) / 128)), dim3(128), 0, st, hoff, coff, ccount, nr,
-                           key_res, mask_res, key_c, mask_c, cread); });
-        if (total > 0) {
-            VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, r0, key_c, cread, coff + nr,
-                          rule, RW, TW, dcap, steps};
-            const unsigned vb = (unsigned)((total + 63) / 64);
-            timed("verify", st, [&] {
-                if (kmax_t == 15)
-                    hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), lds, st, va);
-                else if (kmax_t == 31)
-                    hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), lds, st, va);
-                else
-                    hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
-            });
-        }
-        ReplayArgs ra{probe, NS, key_c, mask_c, dcap, coff, ccount, bmin, scored, lengths, r0, nr, rule,
-                      pos, strand, dist, second, call};
-        timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3((unsigned)((nr + 127) / 128)), dim3(128), 0, st, ra); });
-        HIP_OK(hipGetLastError());
-        if (g_prof_on) {
-            // counters for the roofline: one extra wait per pass, profiling only
-            unsigned long long zero = 0, ssum = 0;
-            int64_t ncand = 0;
-            if (total > 0) {
-                HIP_OK(hipMemcpyAsync(steps_sum, &zero, 8, hipMemcpyHostToDevice, st));
-                hipLaunchKernelGGL(k_sum_u32, dim3(256), dim3(256), 0, st, steps, coff + nr, steps_sum);
-                HIP_OK(hipMemcpyAsync(&ssum, steps_sum, 8, hipMemcpyDeviceToHost, st));
+            const uint32_t maxH = (uint32_t)(sc[0] & 0x7FFFFFFF);
+            int64_t total = sc[1];
+            if (total > PS) {
+                // keep the longest prefix of reads whose hits fit; the rest go to the next chunk
+                hipLaunchKernelGGL(k_fit, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, hoff, nr, PS, misc + 2);
+                int64_t fit = 0;
+                HIP_OK(hipMemcpyAsync(&fit, misc + 2, 8, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
+                if (fit <= 0) return SNAP_ENOMEM;
+                nr = fit;
+                ps.nr = nr;
+                HIP_OK(hipMemcpyAsync(&total, hoff + nr, 8, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
             }
-            HIP_OK(hipMemcpyAsync(&ncand, coff + nr, 8, hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
-            std::lock_guard<std::mutex> g(g_prof_mu);
-            g_ctr.passes += 1;
-            g_ctr.reads += nr;
-            g_ctr.seed_slots += nr * NS;
-            g_ctr.hits += total;
-            g_ctr.locations += ncand;
-            g_ctr.lv_steps += (int64_t)ssum;
-            g_ctr.bases += 0;
+            if (total > 0) {
+                GatherArgs ga{probe, ix->d.positions, ix->d.G, ix->d.s, lengths, ps, hoff, hk};
+                const int64_t gitems = nr * NSp;
+                timed("gather", st, [&] { hipLaunchKernelGGL(k_gather, dim3((unsigned)((gitems + 255) / 256)), dim3(256), 0, st, ga); });
+            }
+            DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, slot_read};
+            {
+                const unsigned lb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
+                timed("dedupe_light", st, [&] { hipLaunchKernelGGL(k_dedupe_light, dim3(lb), dim3(256), 0, st, da); });
+            }
+            if (maxH > 64) {
+                const unsigned hb = (unsigned)std::min<int64_t>(nr, 2048);
+                uint32_t N = 1;
+                while (N < std::min(maxH, cape)) N <<= 1;
+                timed("dedupe_heavy", st, [&] { hipLaunchKernelGGL(k_dedupe_heavy<true>, dim3(hb), dim3(256), (size_t)N * 8, st, da, key_c, cape); });
+                if (maxH > cape)
+                    timed("dedupe_huge", st, [&] { hipLaunchKernelGGL(k_dedupe_heavy<false>, dim3(hb), dim3(256), 0, st, da, key_c, cape); });
+            }
+            tb = scan_tmp_bytes(nr + 1);
+            HIP_OK(scan_excl(scan_tmp, tb, CastU32{ccount, nr}, nr + 1, coff, st));
+            if (total > 0)
+                timed("compact", st, [&] { hipLaunchKernelGGL(k_compact, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, hoff, coff, ccount,
+                                   slot_read, total, key_res, mask_res, key_c, mask_c, cread); });
+            if (total > 0) {
+                VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, coff + nr,
+                              rule, RW, TW, dcap, steps};
+                const unsigned vb = (unsigned)((total + 63) / 64);
+                timed("verify", st, [&] {
+                    if (kmax_t == 15)
+                        hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), lds, st, va);
+                    else if (kmax_t == 31)
+                        hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), lds, st, va);
+                    else
+                        hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
+                });
+            }
+            ReplayArgs ra{probe, key_c, mask_c, dcap, coff, ccount, bmin, scored, lengths, ps, rule, sh,
+                          pending_out, npending_out, pos, strand, dist, second, call};
+            {
+                const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
+                timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rb), dim3(256), 0, st, ra); });
+            }
+            HIP_OK(hipGetLastError());
+            if (g_prof_on) {
+                // counters for the roofline: one extra wait per chunk, profiling only
+                unsigned long long zero = 0, ssum = 0;
+                int64_t ncand = 0;
+                if (total > 0) {
+                    HIP_OK(hipMemcpyAsync(steps_sum, &zero, 8, hipMemcpyHostToDevice, st));
+                    hipLaunchKernelGGL(k_sum_u32, dim3(256), dim3(256), 0, st, steps, coff + nr, steps_sum);
+                    HIP_OK(hipMemcpyAsync(&ssum, steps_sum, 8, hipMemcpyDeviceToHost, st));
+                }
+                HIP_OK(hipMemcpyAsync(&ncand, coff + nr, 8, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
+                std::lock_guard<std::mutex> g(g_prof_mu);
+                g_ctr.passes += 1;
+                g_ctr.reads += (ridx == nullptr) ? nr : 0;
+                g_ctr.seed_slots += nr * NSp;
+                g_ctr.hits += total;
+                g_ctr.locations += ncand;
+                g_ctr.lv_steps += (int64_t)ssum;
+                if (ridx) g_ctr.second_pass_reads += nr;
+            }
+            r0 += nr;
         }
-        r0 += nr;
+        return SNAP_OK;
+    };
+
+    // stage 1: the first pass1_seeds seeds, limit pass1_limit; stage 2: every
+    // seed, limit pass2_limit; stage 3: every seed, full limit. A stage runs on the
+    // reads the previous one could not settle; one that is complete settles all.
+    struct Stage { int seeds, cap; };
+    Stage stages[3];
+    int nst = 0;
+    {
+        const int s1 = tune.pass1_seeds > 0 ? std::min(NS, tune.pass1_seeds) : NS;
+        const int k1 = tune.pass1_limit > 0 && tune.pass1_limit < Kmax ? tune.pass1_limit : KCAP_NONE;
+        stages[nst++] = Stage{s1, k1};
+        if (!(s1 >= NS && k1 == KCAP_NONE)) {
+            const int k2 = tune.pass2_limit > 0 && tune.pass2_limit < Kmax ? tune.pass2_limit : KCAP_NONE;
+            if (k2 != KCAP_NONE && (s1 < NS || k2 > k1)) stages[nst++] = Stage{NS, k2};
+            stages[nst++] = Stage{NS, KCAP_NONE};
+        }
+    }
+    unsigned long long *npend[2] = {npending, npending + 1};
+    uint32_t *plist[2] = {pending, pending + n_reads};
+    const uint32_t *list = nullptr;
+    int64_t list_len = n_reads;
+    for (int k = 0; k < nst && list_len > 0; k++) {
+        const bool last = (k == nst - 1);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)npend[k & 1], 2, 0u);
+        pending_out = plist[k & 1];
+        npending_out = npend[k & 1];
+        int rc = run_pass(list, list_len, stages[k].seeds, stages[k].cap, last ? 1 : 0);
+        if (rc != SNAP_OK) return rc;
+        if (last) break;
+        unsigned long long np = 0;
+        HIP_OK(hipMemcpyAsync(&np, npend[k & 1], 8, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        list = plist[k & 1];
+        list_len = (int64_t)np;
     }
     return SNAP_OK;
 }

@@ -115,6 +115,20 @@ def test_small_workspace_many_passes(snapgpu, oracle_mod, synth_mod):
     assert nbad == 0, rep
 
 
+@pytest.mark.parametrize("seeds,limit,limit2", [(0, 0, 0), (1, 1, 0), (2, 0, 0), (3, 2, 5), (4, 4, 0), (4, 3, 7),
+                                               (6, 8, 9), (32, 63, 0), (1, 0, 3)])
+def test_pass_schedule_invariance(snapgpu, oracle_mod, synth_mod, seeds, limit, limit2):
+    """The pass schedule (stage seeds and verify limits) never changes outputs."""
+    from synth.workloads import MID
+    w, g, reads = _world(synth_mod, MID, 1_000_000, 6_000)
+    old = snapgpu.get_tuning()
+    try:
+        snapgpu.set_tuning(seeds, limit, limit2)
+        _check(snapgpu, oracle_mod, w, g, reads, f"schedule {seeds}/{limit}/{limit2}")
+    finally:
+        snapgpu.set_tuning(*old)
+
+
 def test_batch_composition_invariance(snapgpu, synth_mod):
     """A read's output does not depend on the other reads in the batch or their order."""
     from synth.workloads import MID
