@@ -45,8 +45,10 @@ constexpr int ST_OK = 3;     // looked up (possibly with no hits)
 constexpr int DINF = 0x3FFF;
 constexpr int STREAM_GUARD = 32;   // bases of padding before the packed read stream
 constexpr int64_t CHUNK_READS = 1 << 20;
-constexpr int VERIFY_KMAX = 63;
-constexpr int VERIFY_LMAX = 2048;
+constexpr int VERIFY_KMAX = 1023;   // largest limit d_max(L) + c - 1
+constexpr int VERIFY_LMAX = 16384;  // longest read
+constexpr int LANE_KMAX = 63;       // lane-per-location verify: limit and read length bounds
+constexpr int LANE_LMAX = 512;
 
 struct ProbeRec {
     uint64_t off_f;   // first forward hit (positions index)
@@ -541,8 +543,10 @@ struct VerifyArgs {
     const int64_t *ncand_ptr;   // number of locations (device scalar)
     Rule rule;
     int32_t RW, TW;             // staged words per lane (read, text), guard word included
-    uint8_t *dcap;
+    uint16_t *dcap;
     uint32_t *steps;            // per-location diagonal extensions (profiling only, else null)
+    const uint32_t *list;       // locations routed to this kernel (null: all)
+    const int64_t *nlist_ptr;   // their number when list is set
 };
 
 // Per-lane LDS arrays are laid out [word][lane], so a wave's accesses to its
@@ -592,8 +596,9 @@ template <int KMAX>
 __global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
     extern __shared__ uint32_t sm[];
     const int lane = threadIdx.x;
-    const int64_t k = (int64_t)blockIdx.x * 64 + lane;
-    if (k >= *a.ncand_ptr) return;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    if (idx >= (a.list ? *a.nlist_ptr : *a.ncand_ptr)) return;
+    const int64_t k = a.list ? (int64_t)a.list[idx] : idx;
     Stage st;
     st.lane = lane;
     st.RC = sm;
@@ -666,8 +671,174 @@ __global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
             if (done) { D = e; break; }
         }
     }
-    a.dcap[k] = (uint8_t)D;
+    a.dcap[k] = (uint16_t)D;
     if (a.steps) a.steps[k] = nsteps;
+}
+
+
+// Locations whose read or limit is too large for one lane: one wave per location.
+// Lanes take diagonals (64 per step, as many steps as the round needs), the
+// previous round's furthest rows are read from one LDS buffer and the new ones
+// written to the other, and the read' and text window are staged in LDS once.
+struct WaveVerifyArgs {
+    const uint32_t *gcode, *gmask;
+    uint64_t G;
+    const uint32_t *rcode, *rmask;
+    const int64_t *roff;
+    const int32_t *len;
+    Pass ps;
+    const uint64_t *key;
+    const uint32_t *cread;
+    const uint32_t *list;       // locations of this class (null: all)
+    const int64_t *nlist_ptr;   // how many (or the number of locations when list is null)
+    Rule rule;
+    int32_t RW, TW, KL;         // staged words (guard included) and the largest limit
+    uint16_t *dcap;
+    uint32_t *steps;
+    unsigned long long *next;   // shared work counter (work-stealing launches), null: static stride
+    int32_t grab;               // locations taken per grab
+};
+
+__device__ inline uint32_t lds_w16(const uint32_t *A, int i) {
+    const int w = i >> 4;
+    return funnel(A[w + 1], A[w], (uint32_t)(i & 15) * 2);
+}
+
+__device__ inline int wave_slide(const uint32_t *RC, const uint32_t *RN, const uint32_t *TC, const uint32_t *TN,
+                                 int i, int d, int L, int Tn) {
+    for (;;) {
+        const int j = i + d;
+        const int rem = min(L - i, Tn - j);
+        if (rem <= 0) return i;
+        const uint32_t x = lds_w16(RC, i) ^ lds_w16(TC, j);
+        uint32_t m = ((x | (x >> 1)) & 0x55555555u) | lds_w16(RN, i) | lds_w16(TN, j);
+        if (rem < 16) m |= 0xFFFFFFFFu << (2 * rem);
+        if (m == 0) { i += 16; continue; }
+        return i + (int)(__builtin_ctz(m) >> 1);
+    }
+}
+
+__device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t k, uint32_t *sm) {
+    const int lane = threadIdx.x;
+    uint32_t *RC = sm, *RN = RC + a.RW, *TC = RN + a.RW, *TN = TC + a.TW;
+    int *F0 = reinterpret_cast<int *>(TN + a.TW), *F1 = F0 + (2 * a.KL + 3);
+    const uint64_t key = a.key[k];
+    const int64_t p = (int64_t)(key >> 1);
+    const int strand = (int)(key & 1);
+    const int64_t g = gid(a.ps, a.cread[k]);
+    const int L = a.len[g];
+    const int K = min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
+    const int64_t xb = STREAM_GUARD + a.roff[g];
+    const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
+    const int nrw = (L + 15) >> 4, ntw = (Tn + 15) >> 4;
+    for (int w = lane; w < nrw; w += 64) {
+        uint32_t c, n;
+        if (strand == 0) {
+            c = ext_code16(a.rcode, xb + 16 * w);
+            n = ext_mask16(a.rmask, xb + 16 * w);
+        } else {
+            const int64_t x = xb + L - 16 * (w + 1);
+            c = rc16(ext_code16(a.rcode, x));
+            n = __builtin_bitreverse32(ext_mask16(a.rmask, x)) >> 16;
+        }
+        RC[w] = c;
+        RN[w] = spread16(n);
+    }
+    for (int w = lane; w < ntw; w += 64) {
+        TC[w] = ext_code16(a.gcode, p + 16 * w);
+        TN[w] = spread16(ext_mask16(a.gmask, p + 16 * w));
+    }
+    if (lane == 0) { RC[nrw] = 0; RN[nrw] = 0; TC[ntw] = 0; TN[ntw] = 0; }
+    constexpr int NEG = -(1 << 28);
+    for (int t = lane; t < 2 * K + 3; t += 64) { F0[t] = NEG; F1[t] = NEG; }
+    __syncthreads();
+    int i0 = 0;
+    if (lane == 0) i0 = wave_slide(RC, RN, TC, TN, 0, 0, L, Tn);
+    i0 = __shfl(i0, 0, 64);
+    int D = K + 1;
+    uint32_t nsteps = 1;
+    if (i0 >= L) {
+        D = 0;
+    } else {
+        if (lane == 0) F0[K + 1] = i0;
+        __syncthreads();
+        int *prev = F0, *nxt = F1;
+        for (int e = 1; e <= K; e++) {
+            bool hit = false;
+            for (int d = -e + lane; d <= e; d += 64) {
+                const int idx = d + K + 1;
+                int i = max(prev[idx - 1], max(prev[idx], prev[idx + 1]) + 1);
+                i = min(i, min(L, Tn - d));
+                if (i >= max(0, -d)) {
+                    nsteps++;
+                    i = wave_slide(RC, RN, TC, TN, i, d, L, Tn);
+                    if (i >= L) hit = true;
+                } else {
+                    i = NEG;
+                }
+                nxt[idx] = i;
+            }
+            const bool done = __ballot(hit) != 0;
+            __syncthreads();
+            if (done) { D = e; break; }
+            int *t = prev; prev = nxt; nxt = t;
+        }
+    }
+    if (a.steps) {
+        for (int d = 32; d >= 1; d >>= 1) nsteps += __shfl_xor(nsteps, d, 64);
+    }
+    if (lane == 0) {
+        a.dcap[k] = (uint16_t)D;
+        if (a.steps) a.steps[k] = nsteps;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_verify_wave(WaveVerifyArgs a) {
+    extern __shared__ uint32_t wsm[];
+    const int64_t n = *a.nlist_ptr;
+    if (!a.next) {
+        for (int64_t idx = blockIdx.x; idx < n; idx += gridDim.x)
+            verify_one_wave(a, a.list ? (int64_t)a.list[idx] : idx, wsm);
+        return;
+    }
+    for (;;) {
+        unsigned long long first = 0;
+        if (threadIdx.x == 0) first = atomicAdd(a.next, (unsigned long long)a.grab);
+        first = __shfl((unsigned long long)first, 0, 64);
+        if ((int64_t)first >= n) break;
+        const int64_t last = min((int64_t)first + a.grab, n);
+        for (int64_t idx = (int64_t)first; idx < last; idx++)
+            verify_one_wave(a, a.list ? (int64_t)a.list[idx] : idx, wsm);
+    }
+}
+
+// Split locations by verify tile: lane-per-location when the read and its limit fit
+// one lane's LDS arrays, wave-per-location otherwise.
+__global__ void k_route(const uint32_t *cread, const int32_t *len, Pass ps, Rule rule, const int64_t *ncand_ptr,
+                        int lane_lmax, int lane_kmax, uint32_t *short_list, uint32_t *long_list,
+                        unsigned long long *counts) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = k < *ncand_ptr;
+    bool is_long = false;
+    if (valid) {
+        const int L = len[gid(ps, cread[k])];
+        const int K = min(dmax_for_length(rule, L) + rule.c - 1, ps.Kcap);
+        is_long = L > lane_lmax || K > lane_kmax;
+    }
+    // one atomic per wave and class
+    const int lane = threadIdx.x & 63;
+    const uint64_t bl = __ballot(valid && is_long), bs = __ballot(valid && !is_long);
+    unsigned long long baseL = 0, baseS = 0;
+    if (lane == 0) {
+        if (bl) baseL = atomicAdd(&counts[1], (unsigned long long)__popcll(bl));
+        if (bs) baseS = atomicAdd(&counts[0], (unsigned long long)__popcll(bs));
+    }
+    baseL = __shfl(baseL, 0, 64);
+    baseS = __shfl(baseS, 0, 64);
+    const uint64_t below = (1ull << lane) - 1;
+    if (valid && is_long) long_list[baseL + __popcll(bl & below)] = (uint32_t)k;
+    if (valid && !is_long) short_list[baseS + __popcll(bs & below)] = (uint32_t)k;
 }
 
 __global__ void k_sum_u32(const uint32_t *v, const int64_t *n_ptr, unsigned long long *out) {
@@ -691,7 +862,7 @@ struct ReplayArgs {
     const ProbeRec *pr;
     const uint64_t *key;
     const uint32_t *mask;
-    const uint8_t *dcap;
+    const uint16_t *dcap;
     const int64_t *coff;
     const uint32_t *count;
     uint64_t *bmin;
@@ -934,9 +1105,10 @@ struct Layout {
 };
 
 // pool arrays per slot: hit 8, location key 8 + mask 4 + slot read 4 (by read),
-// compacted key 8 + mask 4 + read 4, bucket minimum 8, capped distance 1, scored flag 1
-constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 1 + 1;
-constexpr int POOL_ARRAYS = 10;
+// compacted key 8 + mask 4 + read 4, bucket minimum 8, capped distance 2, scored
+// flag 1, verify routing lists 4 + 4
+constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 2 + 1 + 4 + 4;
+constexpr int POOL_ARRAYS = 12;
 
 size_t scan_tmp_bytes(int64_t items) {
     size_t b = 0;
@@ -952,7 +1124,7 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
     l.off_rcode = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)nblk);
     l.off_rmask = o; o = align256(o + sizeof(uint32_t) * (size_t)nblk);
-    l.off_misc = o; o = align256(o + 64);
+    l.off_misc = o; o = align256(o + 128);
     l.off_pending = o; o = align256(o + 2 * sizeof(uint32_t) * (size_t)n);
     l.R = R;
     l.off_probe = o; o = align256(o + sizeof(ProbeRec) * (size_t)R * NS);
@@ -1134,8 +1306,11 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     uint32_t *mask_c = (uint32_t *)carve(4 * (size_t)PS);
     uint32_t *cread = (uint32_t *)carve(4 * (size_t)PS);
     uint64_t *bmin = (uint64_t *)carve(8 * (size_t)PS);
-    uint8_t *dcap = (uint8_t *)carve((size_t)PS);
+    uint16_t *dcap = (uint16_t *)carve(2 * (size_t)PS);
     uint8_t *scored = (uint8_t *)carve((size_t)PS);
+    uint32_t *short_list = (uint32_t *)carve(4 * (size_t)PS);
+    uint32_t *long_list = (uint32_t *)carve(4 * (size_t)PS);
+    unsigned long long *route_cnt = (unsigned long long *)(misc + 8);   // two counters
     if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
     // per-location step counts reuse the hit array, dead once locations are compacted
     uint32_t *steps = g_prof_on ? (uint32_t *)hk : nullptr;
@@ -1144,15 +1319,21 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
         const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
         timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk); });
     }
-    const int RW = (std::max(maxL, 1) + 15) / 16 + 1;
-
     // one pass over a list of reads (all reads, or the ones an earlier pass left)
     auto run_pass = [&](const uint32_t *ridx, int64_t list_len, int NSp, int Kcap, int final_pass) -> int {
         const int Kp = std::min(Kmax, Kcap);
-        const int TW = (std::max(maxL, 1) + Kp + 15) / 16 + 1;
-        const int kmax_t = Kp <= 15 ? 15 : (Kp <= 31 ? 31 : 63);
+        // lane-per-location tile: reads up to LANE_LMAX bases with limits up to LANE_KMAX
+        const int lane_L = std::min(maxL, LANE_LMAX), lane_K = std::min(Kp, LANE_KMAX);
+        const bool all_lane = maxL <= LANE_LMAX && Kp <= LANE_KMAX;
+        const int RW = (std::max(lane_L, 1) + 15) / 16 + 1;
+        const int TW = (std::max(lane_L, 1) + lane_K + 15) / 16 + 1;
+        const int kmax_t = lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63);
         const size_t lds = (size_t)64 * 4 * (2 * RW + 2 * TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
-        if (lds > (size_t)lds_max) return SNAP_EINVAL;
+        // wave-per-location tile: any read, any limit
+        const int RWL = (std::max(maxL, 1) + 15) / 16 + 1;
+        const int TWL = (std::max(maxL, 1) + Kp + 15) / 16 + 1;
+        const size_t lds_wave = (size_t)4 * (2 * RWL + 2 * TWL) + (size_t)8 * (2 * Kp + 3);
+        if (lds > (size_t)lds_max || (!all_lane && lds_wave > (size_t)lds_max)) return SNAP_EINVAL;
         for (int64_t r0 = 0; r0 < list_len;) {
             int64_t nr = std::min<int64_t>(R, list_len - r0);
             Pass ps{ridx, r0, nr, NSp, Kcap, final_pass};
@@ -1207,8 +1388,18 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
                 timed("compact", st, [&] { hipLaunchKernelGGL(k_compact, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, hoff, coff, ccount,
                                    slot_read, total, key_res, mask_res, key_c, mask_c, cread); });
             if (total > 0) {
-                VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, coff + nr,
-                              rule, RW, TW, dcap, steps};
+                const int64_t *ncand = coff + nr;
+                const uint32_t *slist = nullptr;
+                const int64_t *nshort = ncand;
+                if (!all_lane) {
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)route_cnt, 4, 0u);
+                    timed("route", st, [&] { hipLaunchKernelGGL(k_route, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, cread, lengths, ps, rule,
+                                       ncand, LANE_LMAX, LANE_KMAX, short_list, long_list, route_cnt); });
+                    slist = short_list;
+                    nshort = (const int64_t *)route_cnt;
+                }
+                VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, ncand,
+                              rule, RW, TW, dcap, steps, slist, nshort};
                 const unsigned vb = (unsigned)((total + 63) / 64);
                 timed("verify", st, [&] {
                     if (kmax_t == 15)
@@ -1218,6 +1409,13 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
                     else
                         hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
                 });
+                if (!all_lane) {
+                    WaveVerifyArgs wa{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
+                                      long_list, (const int64_t *)(route_cnt + 1), rule, RWL, TWL, Kp, dcap, steps,
+                                      nullptr, 1};
+                    const unsigned wb = (unsigned)std::min<int64_t>(total, 8192);
+                    timed("verify_wave", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wa); });
+                }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, coff, ccount, bmin, scored, lengths, ps, rule, sh,
                           pending_out, npending_out, pos, strand, dist, second, call};

@@ -26,8 +26,14 @@ def gpu_align(snapgpu, index, reads, d_max, params, workspace_bytes=None, stream
     return out.numpy()
 
 
-def oracle_align(oracle_mod, oix, reads, wparams, threads=0):
-    res = oix.align_reads(reads, oracle_mod.params_from(wparams), threads=threads)
+def oracle_threads():
+    """Worker threads for the oracle: the host cores, at most 16 (one GPU's share of a box)."""
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def oracle_align(oracle_mod, oix, reads, wparams, threads=None):
+    res = oix.align_reads(reads, oracle_mod.params_from(wparams), threads=threads or oracle_threads())
     return res.fields()
 
 

@@ -99,6 +99,30 @@ def test_long_reads_percent_dmax(snapgpu, oracle_mod, synth_mod):
     _check(snapgpu, oracle_mod, w, g, reads, "long-pct")
 
 
+@pytest.mark.parametrize("len_a,len_b,n", [(300, 3000, 250), (3000, 10000, 16)])
+def test_long_reads_wave_verify(snapgpu, oracle_mod, synth_mod, len_a, len_b, n):
+    """Reads of 300 bp - 10 kb (5% error, half indels, d_max = ceil(0.08 L), limits
+    up to 801): locations go to the wave-per-location verify."""
+    from dataclasses import replace
+    from synth.workloads import BATCHED
+    w = BATCHED.scaled(genome_len=3_000_000, n_reads=n)
+    w = replace(w, reads=replace(w.reads, len_a=len_a, len_b=len_b))
+    g = w.make_genome()
+    reads = w.make_reads(g)
+    out = _check(snapgpu, oracle_mod, w, g, reads, f"long {len_a}-{len_b}")
+    assert (out[4] > 0).mean() > 0.5
+
+
+def test_mixed_lengths_batched_recipe(snapgpu, oracle_mod, synth_mod):
+    """The batched recipe (log-uniform 100 bp - 10 kb) at reduced size: both verify
+    tiles in one call."""
+    from synth.workloads import BATCHED
+    w = BATCHED.scaled(genome_len=3_000_000, n_reads=300)
+    g = w.make_genome()
+    reads = w.make_reads(g)
+    _check(snapgpu, oracle_mod, w, g, reads, "batched-recipe")
+
+
 def test_small_workspace_many_passes(snapgpu, oracle_mod, synth_mod):
     """The minimum workspace forces many internal passes; outputs are unchanged."""
     from synth.workloads import MID
