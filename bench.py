@@ -41,6 +41,196 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def roofline_of(kern, ctr, prefer=None):
+    """Roofline entry of the dominant kernel (or `prefer` if given)."""
+    dom = prefer if prefer in kern else max(kern.items(), key=lambda kv: kv[1][1])[0]
+    launches, total_ms = kern[dom]
+    avg_s = total_ms / 1000.0 / launches
+    per_launch = 1.0 / launches
+    if dom == "probe":
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = ctr["seed_slots"] * PROBE_BYTES_PER_SLOT * per_launch / 1e9
+    elif dom == "gather":
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = (ctr["seed_slots"] * GATHER_BYTES_PER_SLOT + ctr["hits"] * GATHER_BYTES_PER_HIT) * per_launch / 1e9
+    elif dom.startswith("dedupe"):
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = (ctr["hits"] * DEDUPE_BYTES_PER_HIT + ctr["locations"] * DEDUPE_BYTES_PER_LOC) * per_launch / 1e9
+    elif dom.startswith("verify"):
+        # every verify kernel of the step shares the step counter; split it by time
+        vt = sum(v[1] for k, v in kern.items() if k.startswith("verify"))
+        share = total_ms / vt if vt > 0 else 1.0
+        bound, unit, peak = "alu", "TOP/s", VALU_PEAK_TOPS
+        work = ctr["lv_steps"] * share * VERIFY_OPS_PER_STEP * per_launch / 1e12
+    else:
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        work = float("nan")
+    achieved = work / avg_s
+    return {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 5), "avg_launch_ms": round(total_ms / launches, 4), "launches": launches}
+
+
+def cpu_baseline(g, reads, w, got, seconds, log_fn=None):
+    """The oracle on a seeded sample sized to about `seconds` of CPU time; checks
+    the GPU outputs of the sample bit-exact first."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t = time.time()
+    oix = oracle.Index(g, w.params.seed_len)
+    log(f"oracle index in {time.time() - t:.1f}s")
+    op = oracle.params_from(w.params)
+    rng = np.random.default_rng(7)
+    probe_n = min(reads.n, 2000)
+    idx = np.sort(rng.choice(reads.n, probe_n, replace=False))
+    sub = reads.subset(idx)
+    t = time.perf_counter()
+    res = oix.align_reads(sub, op, threads=threads)
+    dt = time.perf_counter() - t
+    rate = probe_n / max(dt, 1e-9)
+    n_s = int(min(reads.n, max(probe_n, rate * seconds)))
+    if n_s > probe_n:
+        idx = np.sort(rng.choice(reads.n, n_s, replace=False))
+        sub = reads.subset(idx)
+        t = time.perf_counter()
+        res = oix.align_reads(sub, op, threads=threads)
+        dt = time.perf_counter() - t
+    oix.close()
+    mism = sum(int(np.count_nonzero(np.asarray(a)[idx].astype(np.int64) != np.asarray(b).astype(np.int64)))
+               for a, b in zip(got, res.fields()))
+    if mism:
+        print(json.dumps({"error": f"GPU output differs from the oracle on {mism} fields of the sample"}), flush=True)
+        sys.exit(1)
+    return {"value": round(len(idx) / dt, 1), "unit": "reads/s", "cores": res.threads, "kind": "oracle",
+            "sample": f"{len(idx)} seeded-random reads of the {w.name} workload, {dt:.1f}s, "
+                      f"bit-exact vs GPU on all five outputs"}
+
+
+LENGTH_BUCKETS = [(0, 300), (301, 1000), (1001, 3000), (3001, 1 << 30)]
+
+
+def bench_batched(args, w, dev):
+    """Reads of mixed length (100 bp - 10 kb): per-length-bucket snap_align calls
+    (the plain form) vs one snap_align_batched call with the autotuned schedule."""
+    import torch
+    import paper_1111_5572_amd as snapgpu
+    from paper_1111_5572_amd import autotune
+
+    t = time.time()
+    g = w.make_genome()
+    log(f"genome {w.name}: {len(g)} bases in {time.time() - t:.1f}s")
+    t = time.time()
+    reads = w.make_reads(g)
+    log(f"reads: {reads.n} ({int(reads.bases.shape[0])} bases) in {time.time() - t:.1f}s")
+    t = time.time()
+    gix = snapgpu.Index(g, w.params.seed_len)
+    index_s = time.time() - t
+    sizes = gix.sizes()
+    log(f"index built and resident in {index_s:.1f}s: {sizes}")
+    params = snapgpu.params_from(w.params)
+    d_max = w.params.d_max
+
+    # plain form, one call per length bucket (each bucket resident on the device)
+    parts = []
+    for lo, hi in LENGTH_BUCKETS:
+        idx = np.nonzero((reads.lengths >= lo) & (reads.lengths <= hi))[0]
+        if len(idx) == 0:
+            continue
+        sub = reads.subset(idx)
+        rb = torch.from_numpy(sub.bases).to(dev)
+        ln = torch.from_numpy(sub.lengths).to(dev)
+        ml = int(sub.lengths.max())
+        wb = snapgpu.workspace_bytes(gix, sub.n, int(sub.bases.shape[0]), ml, d_max, params)
+        ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+        parts.append((idx, rb, ln, ml, ws, None))
+        del sub
+    log("buckets: " + ", ".join(f"{len(p[0])}" for p in parts))
+
+    def run_plain(outs):
+        for k, (idx, rb, ln, ml, ws, _) in enumerate(parts):
+            outs[k] = snapgpu.align(gix, rb, ln, d_max, params, out=outs[k], workspace=ws, max_len=ml)
+        return outs
+
+    outs = run_plain([None] * len(parts))
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        run_plain(outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_plain(outs)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / args.steps
+    plain_out = [np.zeros(reads.n, dt) for dt in (np.int64, np.int8, np.int32, np.int32, np.int8)]
+    for (idx, *_), o in zip(parts, outs):
+        for f, x in zip(plain_out, o.numpy()):
+            f[idx] = x
+    log(f"plain per-bucket: {plain_s * 1000:.1f} ms/step, {reads.n / plain_s:,.0f} reads/s")
+    del parts, outs
+    torch.cuda.empty_cache()
+
+    # batched form over the whole batch
+    rb = torch.from_numpy(reads.bases).to(dev)
+    ln = torch.from_numpy(reads.lengths).to(dev)
+    ml = int(reads.lengths.max())
+    tuning = None
+    tune_info = None
+    if not args.no_autotune:
+        tune_info = autotune.tune(gix, rb, ln, d_max, params, batched=True, sample_reads=min(reads.n, 100_000),
+                                  table_path=None, log=log)
+        tuning = tuple(tune_info["tuning"])
+        log(f"autotuned schedule {tuning}")
+    wb = snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), ml, d_max, params) * 2
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    out = snapgpu.align(gix, rb, ln, d_max, params, workspace=ws, max_len=ml, batched=True, tuning=tuning)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True, tuning=tuning)
+    torch.cuda.synchronize()
+    snapgpu.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True, tuning=tuning)
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / args.steps
+    kern = snapgpu.profile_end()
+    ctr = snapgpu.profile_counters()
+    got = out.numpy()
+    same = all(np.array_equal(np.asarray(a).astype(np.int64), np.asarray(b).astype(np.int64))
+               for a, b in zip(got, plain_out))
+    log(f"batched: {batched_s * 1000:.1f} ms/step, {reads.n / batched_s:,.0f} reads/s, identical to plain: {same}")
+    log("kernels: " + ", ".join(f"{k} {v[1] / max(v[0], 1):.3f} ms x{v[0]}" for k, v in kern.items()))
+    if not same:
+        print(json.dumps({"error": "batched and per-bucket plain outputs differ"}), flush=True)
+        sys.exit(1)
+    roofline = roofline_of(kern, ctr)
+    roofline["traffic"] = None
+    cpu = None if args.no_cpu_baseline else cpu_baseline(g, reads, w, got, args.cpu_seconds)
+    calls = np.bincount(got[4].astype(np.int64), minlength=3)
+    line = {
+        "metric": "reads aligned/s", "value": round(reads.n / batched_s, 1), "unit": "reads/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(batched_s * 1000, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded genome and simulated reads; no real data)",
+        "config": {"workload": "batched", "genome_bases": len(g), "reads": reads.n,
+                   "read_len": f"{int(reads.lengths.min())}-{int(reads.lengths.max())} log-uniform",
+                   "seed_len": w.params.seed_len, "d_max": "max(8, ceil(0.08 L))", "conf_c": w.params.conf_c,
+                   "max_hits": w.params.max_hits, "form": "batched (one work-stealing verify launch per pass)"},
+        "gbases_per_s": round(float(reads.bases.shape[0]) / batched_s / 1e9, 4),
+        "plain_per_bucket": {"reads_per_s": round(reads.n / plain_s, 1), "ms_per_step": round(plain_s * 1000, 3),
+                             "buckets": [list(b) for b in LENGTH_BUCKETS]},
+        "speedup_vs_per_bucket": round(plain_s / batched_s, 3),
+        "autotune": tune_info,
+        "index_build_s": round(index_s, 2), "index_device_bytes": sizes["device_bytes"],
+        "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
+        "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
+        "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    gix.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +241,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -64,10 +256,12 @@ def main():
     from synth.workloads import WORKLOADS
 
     w = WORKLOADS[args.workload]
-    if args.reads:
-        w = w.scaled(n_reads=args.reads)
+    if args.reads or args.genome_len:
+        w = w.scaled(genome_len=args.genome_len or None, n_reads=args.reads or None)
     dev = torch.device("cuda:0")
     snapgpu.lib()
+    if args.workload == "batched":
+        return bench_batched(args, w, dev)
 
     t = time.time()
     g = w.make_genome()

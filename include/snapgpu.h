@@ -162,11 +162,27 @@ typedef struct {
     int32_t pass1_seeds;
     int32_t pass1_limit;
     int32_t pass2_limit;
-    int32_t reserved;
+    int32_t lane_max_len;   /* verify tile: reads up to this length (and limits up to 63) get one lane
+                               per location, longer ones a wave per location; 0 = 512 (the maximum) */
 } snap_tuning;
 
 int snap_set_tuning(const snap_tuning *t);
 int snap_get_tuning(snap_tuning *t);
+
+/*
+ * Batched form of snap_align for batches that mix read lengths (100 bp to 10 kb):
+ * identical outputs, same arguments and errors, plus an explicit schedule
+ * (tuning may be NULL for the process-wide one). Per pass, every location of the
+ * batch is verified by ONE persistent work-stealing launch: each wave first takes
+ * long locations one at a time (a wave per location), then groups of 64 short
+ * locations (a lane per location) in guided chunks of about half the remaining
+ * groups per wave (the range rule of Section 2.3). A larger workspace lets a pass
+ * cover more of the batch.
+ */
+int snap_align_batched(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
+                       int32_t d_max, const snap_params *p, const snap_tuning *tuning, int64_t *pos,
+                       int8_t *strand, int32_t *dist, int32_t *second, int8_t *call, void *workspace,
+                       size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------- instrumentation */
 
@@ -197,7 +213,8 @@ typedef struct {
     int64_t hits;         /* seed hits gathered (h_max-passing seeds) */
     int64_t locations;    /* distinct (strand, p) locations verified */
     int64_t lv_steps;     /* diagonal extensions run by the verify kernel */
-    int64_t second_pass_reads; /* reads a first pass left to the complete pass */
+    int64_t second_pass_reads; /* reads a first pass left to a later pass */
+    int64_t requests;     /* long-read locations verified on request in the final pass */
 } snap_counters;
 
 int snap_profile_counters(snap_counters *out);

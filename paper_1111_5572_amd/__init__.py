@@ -45,24 +45,27 @@ class KernelTime(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "pass2_limit", "reserved")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "pass2_limit", "lane_max_len")]
+
+    def astuple(self):
+        return (int(self.pass1_seeds), int(self.pass1_limit), int(self.pass2_limit), int(self.lane_max_len))
 
 
-def set_tuning(pass1_seeds: int, pass1_limit: int, pass2_limit: int = 0):
-    """Output-invariant pass schedule (see snap_set_tuning); 0 = no cap."""
-    _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, pass2_limit, 0))),
+def set_tuning(pass1_seeds: int, pass1_limit: int, pass2_limit: int = 0, lane_max_len: int = 0):
+    """Output-invariant pass schedule and verify tile bound (see snap_set_tuning); 0 = default."""
+    _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, pass2_limit, lane_max_len))),
            "snap_set_tuning")
 
 
-def get_tuning() -> tuple[int, int, int]:
+def get_tuning() -> tuple[int, int, int, int]:
     t = Tuning()
     _check(lib().snap_get_tuning(ctypes.byref(t)), "snap_get_tuning")
-    return int(t.pass1_seeds), int(t.pass1_limit), int(t.pass2_limit)
+    return t.astuple()
 
 
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "second_pass_reads")]
+                ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "second_pass_reads", "requests")]
 
 
 def lib():
@@ -103,6 +106,9 @@ def lib():
         L.snap_set_tuning.restype = ctypes.c_int
         L.snap_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.snap_get_tuning.restype = ctypes.c_int
+        L.snap_align_batched.argtypes = [P, P, P, i64, i32, ctypes.POINTER(Params), ctypes.POINTER(Tuning),
+                                         P, P, P, P, P, P, sz, P]
+        L.snap_align_batched.restype = ctypes.c_int
         L.snap_debug_copy.argtypes = [P, P, u64, P]
         L.snap_debug_copy.restype = ctypes.c_int
         _lib = L
@@ -200,9 +206,11 @@ def workspace_bytes(index: Index, n_reads: int, total_bases: int, max_len: int, 
 
 
 def align(index: Index, reads, lengths, d_max: int, params: Params | None = None, out: Alignment | None = None,
-          workspace=None, stream=None, max_len: int | None = None) -> Alignment:
-    """snap_align on device tensors: reads (uint8, concatenated ASCII) and lengths
-    (int32). Returns device tensors; they are valid once `stream` is synchronized."""
+          workspace=None, stream=None, max_len: int | None = None, batched: bool = False,
+          tuning: "Tuning | tuple | None" = None) -> Alignment:
+    """snap_align (or snap_align_batched when batched=True) on device tensors:
+    reads (uint8, concatenated ASCII) and lengths (int32). Returns device tensors;
+    they are valid once `stream` is synchronized."""
     import torch
     params = params or default_params()
     n = int(lengths.shape[0])
@@ -217,6 +225,16 @@ def align(index: Index, reads, lengths, d_max: int, params: Params | None = None
         if wb == 0 and n:
             raise SnapError(SNAP_EINVAL, "snap_align_workspace_bytes")
         workspace = torch.empty(max(wb, 256), dtype=torch.uint8, device=dev)
+    if batched:
+        if isinstance(tuning, tuple):
+            tuning = Tuning(*tuning)
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        code = lib().snap_align_batched(index.handle, reads.data_ptr(), lengths.data_ptr(), n, d_max,
+                                        ctypes.byref(params), tp, out.pos.data_ptr(), out.strand.data_ptr(),
+                                        out.dist.data_ptr(), out.second.data_ptr(), out.call.data_ptr(),
+                                        workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
+        _check(code, "snap_align_batched")
+        return out
     code = lib().snap_align(index.handle, reads.data_ptr(), lengths.data_ptr(), n, d_max, ctypes.byref(params),
                             out.pos.data_ptr(), out.strand.data_ptr(), out.dist.data_ptr(), out.second.data_ptr(),
                             out.call.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))

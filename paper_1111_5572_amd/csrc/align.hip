@@ -544,6 +544,7 @@ struct VerifyArgs {
     Rule rule;
     int32_t RW, TW;             // staged words per lane (read, text), guard word included
     uint16_t *dcap;
+    int16_t *vlim;              // the limit each location was verified with
     uint32_t *steps;            // per-location diagonal extensions (profiling only, else null)
     const uint32_t *list;       // locations routed to this kernel (null: all)
     const int64_t *nlist_ptr;   // their number when list is set
@@ -593,12 +594,8 @@ __device__ inline int slide(const Stage &st, int i, int d, int L, int Tn) {
 // Furthest-reaching rows per diagonal, e = 0, 1, ..., limit; returns D if D <= K,
 // else K + 1.
 template <int KMAX>
-__global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
-    extern __shared__ uint32_t sm[];
-    const int lane = threadIdx.x;
-    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
-    if (idx >= (a.list ? *a.nlist_ptr : *a.ncand_ptr)) return;
-    const int64_t k = a.list ? (int64_t)a.list[idx] : idx;
+__device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm) {
+    const int lane = threadIdx.x & 63;
     Stage st;
     st.lane = lane;
     st.RC = sm;
@@ -672,9 +669,19 @@ __global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
         }
     }
     a.dcap[k] = (uint16_t)D;
+    a.vlim[k] = (int16_t)K;
     if (a.steps) a.steps[k] = nsteps;
 }
 
+
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
+    extern __shared__ uint32_t sm[];
+    const int lane = threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    if (idx >= (a.list ? *a.nlist_ptr : *a.ncand_ptr)) return;
+    verify_lane<KMAX>(a, a.list ? (int64_t)a.list[idx] : idx, sm);
+}
 
 // Locations whose read or limit is too large for one lane: one wave per location.
 // Lanes take diagonals (64 per step, as many steps as the round needs), the
@@ -694,9 +701,11 @@ struct WaveVerifyArgs {
     Rule rule;
     int32_t RW, TW, KL;         // staged words (guard included) and the largest limit
     uint16_t *dcap;
+    int16_t *vlim;
     uint32_t *steps;
     unsigned long long *next;   // shared work counter (work-stealing launches), null: static stride
     int32_t grab;               // locations taken per grab
+    const int32_t *req_lim;     // per list entry: the limit to verify with (null: the read's full limit)
 };
 
 __device__ inline uint32_t lds_w16(const uint32_t *A, int i) {
@@ -718,7 +727,8 @@ __device__ inline int wave_slide(const uint32_t *RC, const uint32_t *RN, const u
     }
 }
 
-__device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t k, uint32_t *sm) {
+__device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t idx, uint32_t *sm) {
+    const int64_t k = a.list ? (int64_t)a.list[idx] : idx;
     const int lane = threadIdx.x;
     uint32_t *RC = sm, *RN = RC + a.RW, *TC = RN + a.RW, *TN = TC + a.TW;
     int *F0 = reinterpret_cast<int *>(TN + a.TW), *F1 = F0 + (2 * a.KL + 3);
@@ -727,9 +737,9 @@ __device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t k, uint3
     const int strand = (int)(key & 1);
     const int64_t g = gid(a.ps, a.cread[k]);
     const int L = a.len[g];
-    const int K = min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
+    const int K = a.req_lim ? a.req_lim[idx] : min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
     const int64_t xb = STREAM_GUARD + a.roff[g];
-    const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
+    const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + max(K, 0));
     const int nrw = (L + 15) >> 4, ntw = (Tn + 15) >> 4;
     for (int w = lane; w < nrw; w += 64) {
         uint32_t c, n;
@@ -750,7 +760,7 @@ __device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t k, uint3
     }
     if (lane == 0) { RC[nrw] = 0; RN[nrw] = 0; TC[ntw] = 0; TN[ntw] = 0; }
     constexpr int NEG = -(1 << 28);
-    for (int t = lane; t < 2 * K + 3; t += 64) { F0[t] = NEG; F1[t] = NEG; }
+    for (int t = lane; t < 2 * max(K, 0) + 3; t += 64) { F0[t] = NEG; F1[t] = NEG; }
     __syncthreads();
     int i0 = 0;
     if (lane == 0) i0 = wave_slide(RC, RN, TC, TN, 0, 0, L, Tn);
@@ -789,7 +799,8 @@ __device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t k, uint3
     }
     if (lane == 0) {
         a.dcap[k] = (uint16_t)D;
-        if (a.steps) a.steps[k] = nsteps;
+        a.vlim[k] = (int16_t)K;
+        if (a.steps) a.steps[k] = (a.req_lim ? a.steps[k] : 0u) + nsteps;
     }
     __syncthreads();
 }
@@ -798,8 +809,7 @@ __global__ __launch_bounds__(64) void k_verify_wave(WaveVerifyArgs a) {
     extern __shared__ uint32_t wsm[];
     const int64_t n = *a.nlist_ptr;
     if (!a.next) {
-        for (int64_t idx = blockIdx.x; idx < n; idx += gridDim.x)
-            verify_one_wave(a, a.list ? (int64_t)a.list[idx] : idx, wsm);
+        for (int64_t idx = blockIdx.x; idx < n; idx += gridDim.x) verify_one_wave(a, idx, wsm);
         return;
     }
     for (;;) {
@@ -808,9 +818,64 @@ __global__ __launch_bounds__(64) void k_verify_wave(WaveVerifyArgs a) {
         first = __shfl((unsigned long long)first, 0, 64);
         if ((int64_t)first >= n) break;
         const int64_t last = min((int64_t)first + a.grab, n);
-        for (int64_t idx = (int64_t)first; idx < last; idx++)
-            verify_one_wave(a, a.list ? (int64_t)a.list[idx] : idx, wsm);
+        for (int64_t idx = (int64_t)first; idx < last; idx++) verify_one_wave(a, idx, wsm);
     }
+}
+
+
+// Batched form: one persistent launch verifies every location of a pass. Each wave
+// first takes long locations one at a time (wave tile), then groups of 64 short
+// locations (lane tile) in guided chunks of about half the remaining groups
+// divided by the number of waves, at least one (the range rule of Section 2.3).
+struct StealArgs {
+    VerifyArgs va;               // lane tile over the short list
+    WaveVerifyArgs wa;           // wave tile over the long list
+    unsigned long long *next;    // [0] long cursor, [1] short-group cursor
+    int32_t nwaves;
+};
+
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_verify_steal(StealArgs a) {
+    extern __shared__ uint32_t ssm[];
+    const int lane = threadIdx.x;
+    const int64_t nlong = *a.wa.nlist_ptr;
+    for (;;) {
+        unsigned long long i = 0;
+        if (lane == 0) i = atomicAdd(&a.next[0], 1ull);
+        i = __shfl(i, 0, 64);
+        if ((int64_t)i >= nlong) break;
+        verify_one_wave(a.wa, (int64_t)i, ssm);
+    }
+    const int64_t nshort = *a.va.nlist_ptr;
+    const int64_t ngroups = (nshort + 63) / 64;
+    for (;;) {
+        unsigned long long first = 0, take = 1;
+        if (lane == 0) {
+            const long long seen = (long long)*(volatile unsigned long long *)&a.next[1];
+            const long long rem = (long long)ngroups - seen;
+            take = rem > 2ll * a.nwaves ? (unsigned long long)(rem / (2ll * a.nwaves)) : 1ull;
+            first = atomicAdd(&a.next[1], take);
+        }
+        first = __shfl(first, 0, 64);
+        take = __shfl(take, 0, 64);
+        if ((int64_t)first >= ngroups) break;
+        const int64_t last = min((int64_t)(first + take), ngroups);
+        for (int64_t gi = (int64_t)first; gi < last; gi++) {
+            const int64_t idx = gi * 64 + lane;
+            if (idx < nshort) verify_lane<KMAX>(a.va, (int64_t)a.va.list[idx], ssm);
+        }
+    }
+}
+
+// Locations left for verification on request: capped distance unknown above -1.
+__global__ void k_mark_unverified(const uint32_t *list, const int64_t *n_ptr, uint16_t *dcap, int16_t *vlim,
+                                  uint32_t *steps) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *n_ptr) return;
+    const uint32_t k = list[i];
+    dcap[k] = 0xFFFF;
+    vlim[k] = -1;
+    if (steps) steps[k] = 0;
 }
 
 // Split locations by verify tile: lane-per-location when the read and its limit fit
@@ -863,6 +928,7 @@ struct ReplayArgs {
     const uint64_t *key;
     const uint32_t *mask;
     const uint16_t *dcap;
+    const int16_t *vlim;
     const int64_t *coff;
     const uint32_t *count;
     uint64_t *bmin;
@@ -871,8 +937,14 @@ struct ReplayArgs {
     Pass ps;
     Rule rule;
     Shifts sh;
-    uint32_t *pending;          // reads this pass could not settle
+    uint32_t *pending;          // reads this pass could not settle (non-final passes)
     unsigned long long *npending;
+    const uint32_t *rlist;      // chunk reads to replay (null: all nr)
+    const unsigned long long *rlist_n;
+    uint32_t *req_loc;          // final pass: the location each unsettled read needs verified,
+    int32_t *req_lim;           //   the limit to verify it with,
+    uint32_t *req_read;         //   and the read (replayed again once it is verified)
+    unsigned long long *nreq;
     int64_t *pos;
     int8_t *strand;
     int32_t *dist, *second;
@@ -952,23 +1024,33 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
     return v;
 }
 
+// EditDistance(Read, Reference[p_k], lim) from what is known about location k: its
+// capped distance dc = min(D, vl + 1) for the limit vl it was verified with.
+// Returns the distance, -1 for the special value, or -2 when it is not known yet.
+__device__ inline int ed_answer(int dc, int vl, int lim) {
+    if (dc <= vl) return dc <= lim ? dc : -1;
+    return lim <= vl ? -1 : -2;
+}
+
 // Algorithm 1's control flow over the seed masks and capped distances of one read,
-// one wave per read. EditDistance(Read, Reference[p], d_limit) is answered from
-// the capped distance dc = min(D, Kv + 1): D if dc <= d_limit, the special value if
-// dc > d_limit and d_limit <= Kv; with dc = Kv + 1 < d_limit + 1 the pass lacks
-// the answer and leaves the read to the next pass. The phase that scores every
-// remaining location only changes state at locations whose call returns a
-// distance, so it scans for the next such location in selection order (vote count
-// descending, then p, then strand) instead of visiting each one.
+// one wave per read. A call is answered from the location's capped distance; when
+// that does not decide it (the location was verified with a limit below the one
+// Algorithm 1 asks for), a non-final pass leaves the read to the next pass and
+// the final pass requests verification of exactly that location with exactly that
+// limit, then replays the read once the answer exists. The phase that scores every
+// remaining location only changes state at calls that return a distance, so it
+// scans for the next such location in selection order (vote count descending,
+// then p, then strand) instead of visiting each one.
 __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r = wave; r < a.ps.nr; r += nwaves) {
+    const int64_t nlist = a.rlist ? (int64_t)*a.rlist_n : a.ps.nr;
+    for (int64_t ri = wave; ri < nlist; ri += nwaves) {
+        const int64_t r = a.rlist ? (int64_t)a.rlist[ri] : ri;
         const int64_t g = gid(a.ps, r);
         const int L = a.len[g];
         const int dmax = dmax_for_length(a.rule, L), c = a.rule.c;
-        const int Kv = min(dmax + c - 1, a.ps.Kcap);
         const int NS = a.ps.NS;
         const int64_t base = a.coff[r];
         const int64_t C = a.count[r];
@@ -980,6 +1062,8 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         const int round0 = L / a.rule.s;
         int t = 0, call = -1;
         bool looked = false, all_over = true, ended = false, unresolved = false;
+        int64_t need_k = -1;
+        int need_lim = 0;
         uint32_t prefix = 0;
         for (int i = 0; i < NS; i++) {
             const int status = a.pr[r * NS + i].status;
@@ -1003,10 +1087,10 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             if (best) {
                 const int64_t kb = (int64_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
                 const int lim = d_limit(st, dmax, c);
-                const int dc = a.dcap[base + kb];
-                if (dc > Kv && lim > Kv) { unresolved = true; break; }
+                const int res = ed_answer(a.dcap[base + kb], a.vlim[base + kb], lim);
+                if (res == -2) { unresolved = true; need_k = kb; need_lim = lim; break; }
                 if (lane == 0) a.scored[base + kb] = 1;
-                if (dc <= lim) wave_record(a, base, kb, dc, st, lane);
+                if (res >= 0) wave_record(a, base, kb, res, st, lane);
             }
             if (st.d_best < c && st.d_second < st.d_best + c) {
                 call = SNAP_MULTIPLE;
@@ -1019,21 +1103,28 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                     for (int64_t c0 = 0; c0 < C && !unresolved; c0 += 64) {
                         const int64_t k = c0 + lane;
                         bool in = false;
-                        int dc = 0;
+                        int dc = 0, vl = 0;
                         if (k < C && !a.scored[base + k] && __builtin_popcount(a.mask[base + k] & prefix) == lev) {
                             in = true;
                             dc = a.dcap[base + k];
+                            vl = a.vlim[base + k];
                         }
                         for (;;) {
                             const int lim = d_limit(st, dmax, c);
-                            const bool un = in && dc > Kv && lim > Kv;
-                            const bool ev = in && dc <= lim;
-                            const uint64_t bits = __ballot(un || ev);
+                            const int res = in ? ed_answer(dc, vl, lim) : -1;
+                            const bool un = res == -2;
+                            const uint64_t bits = __ballot(res != -1);
                             if (!bits) break;
                             const int j = __builtin_ctzll(bits);
-                            if ((__ballot(un) >> j) & 1) { unresolved = true; break; }
-                            const int dj = __shfl(dc, j, 64);
+                            if ((__ballot(un) >> j) & 1) {
+                                unresolved = true;
+                                need_k = c0 + j;
+                                need_lim = lim;
+                                break;
+                            }
+                            const int dj = __shfl(res, j, 64);
                             wave_record(a, base, c0 + j, dj, st, lane);
+                            // the calls before j returned the special value: scored, no effect
                             if (lane <= j) in = false;
                         }
                     }
@@ -1045,8 +1136,17 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         // all slots of this pass used and the read still has seeds to try
         if (!ended && !unresolved && NS < seeds_for_length(a.rule, L) && seed_offset(a.sh, a.rule.s, L, NS) >= 0)
             unresolved = true;
-        if (unresolved && !a.ps.final_pass) {
-            if (lane == 0) a.pending[atomicAdd(a.npending, 1ull)] = (uint32_t)g;
+        if (unresolved) {
+            if (lane == 0) {
+                if (!a.ps.final_pass || need_k < 0) {
+                    a.pending[atomicAdd(a.npending, 1ull)] = (uint32_t)g;
+                } else {
+                    const unsigned long long q = atomicAdd(a.nreq, 1ull);
+                    a.req_loc[q] = (uint32_t)(base + need_k);
+                    a.req_lim[q] = need_lim;
+                    a.req_read[q] = (uint32_t)r;
+                }
+            }
             continue;
         }
         if (call < 0) {
@@ -1098,17 +1198,17 @@ struct Layout {
     // batch part
     size_t off_roff, off_rcode, off_rmask, off_misc, off_pending;
     // chunk part
-    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan, off_pool;
+    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan, off_req, off_pool;
     int64_t R;             // reads per chunk
     int64_t pool_slots;    // hit / location slots per chunk
     size_t total;
 };
 
 // pool arrays per slot: hit 8, location key 8 + mask 4 + slot read 4 (by read),
-// compacted key 8 + mask 4 + read 4, bucket minimum 8, capped distance 2, scored
-// flag 1, verify routing lists 4 + 4
-constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 2 + 1 + 4 + 4;
-constexpr int POOL_ARRAYS = 12;
+// compacted key 8 + mask 4 + read 4, bucket minimum 8, capped distance 2, verified
+// limit 2, scored flag 1, verify routing lists 4 + 4
+constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 2 + 2 + 1 + 4 + 4;
+constexpr int POOL_ARRAYS = 13;
 
 size_t scan_tmp_bytes(int64_t items) {
     size_t b = 0;
@@ -1124,7 +1224,7 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
     l.off_rcode = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)nblk);
     l.off_rmask = o; o = align256(o + sizeof(uint32_t) * (size_t)nblk);
-    l.off_misc = o; o = align256(o + 128);
+    l.off_misc = o; o = align256(o + 256);
     l.off_pending = o; o = align256(o + 2 * sizeof(uint32_t) * (size_t)n);
     l.R = R;
     l.off_probe = o; o = align256(o + sizeof(ProbeRec) * (size_t)R * NS);
@@ -1133,6 +1233,7 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     l.off_ccount = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
     l.off_coff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
     l.off_scan = o; o = align256(o + std::max(scan_tmp_bytes(R + 1), scan_tmp_bytes(n + 1)));
+    l.off_req = o; o = align256(o + 4 * sizeof(uint32_t) * (size_t)R);   // location, limit, two read lists
     const int64_t minslots = (int64_t)NS * hmax;
     if (pool_slots < minslots) pool_slots = minslots;
     l.pool_slots = pool_slots;
@@ -1181,7 +1282,7 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {4, 4, 0, 0};   // seeds and limit of stage 1, limit of stage 2
+snap_tuning g_tune = {4, 4, 0, 0};   // seeds and limit of stage 1, limit of stage 2, lane-tile read bound
 
 constexpr int KCAP_NONE = 1 << 20;
 
@@ -1196,7 +1297,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->pass2_limit < 0 || t->lane_max_len < 0) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -1218,9 +1319,11 @@ extern "C" size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_rea
     return make_layout(n_reads, total_bases, NS, p->max_hits, R, R * 24).total;
 }
 
-extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
-                          int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,
-                          int32_t *second, int8_t *call, void *workspace, size_t ws_bytes, void *stream) {
+namespace {
+
+int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads, int32_t d_max,
+               const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist, int32_t *second, int8_t *call,
+               void *workspace, size_t ws_bytes, void *stream, bool batched, const snap_tuning *tuning) {
     if (!ix || n_reads < 0 || d_max < 0 || !valid_params(p)) return SNAP_EINVAL;
     if (n_reads == 0) return SNAP_OK;
     if (!reads || !lengths || !pos || !strand || !dist || !second || !call || !workspace) return SNAP_EINVAL;
@@ -1229,10 +1332,14 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     const Rule rule = make_rule(ix, d_max, p);
     const Shifts sh = make_shifts(ix->d.s);
     snap_tuning tune;
-    {
+    if (tuning) {
+        tune = *tuning;
+    } else {
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.pass2_limit < 0 || tune.lane_max_len < 0) return SNAP_EINVAL;
+    const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
     int dev = 0, lds_max = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1295,6 +1402,9 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     uint32_t *ccount = (uint32_t *)(ws + l.off_ccount);
     int64_t *coff = (int64_t *)(ws + l.off_coff);
     void *scan_tmp = ws + l.off_scan;
+    uint32_t *req_loc = (uint32_t *)(ws + l.off_req);
+    int32_t *req_lim = (int32_t *)(req_loc + R);
+    uint32_t *req_list[2] = {(uint32_t *)(req_lim + R), (uint32_t *)(req_lim + R) + R};
     const int64_t PS = l.pool_slots;
     char *pool = ws + l.off_pool;
     auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
@@ -1307,14 +1417,25 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     uint32_t *cread = (uint32_t *)carve(4 * (size_t)PS);
     uint64_t *bmin = (uint64_t *)carve(8 * (size_t)PS);
     uint16_t *dcap = (uint16_t *)carve(2 * (size_t)PS);
+    int16_t *vlim = (int16_t *)carve(2 * (size_t)PS);
     uint8_t *scored = (uint8_t *)carve((size_t)PS);
     uint32_t *short_list = (uint32_t *)carve(4 * (size_t)PS);
     uint32_t *long_list = (uint32_t *)carve(4 * (size_t)PS);
     unsigned long long *route_cnt = (unsigned long long *)(misc + 8);   // two counters
+    unsigned long long *steal_next = (unsigned long long *)(misc + 10);  // two cursors
+    unsigned long long *nreq = (unsigned long long *)(misc + 12);        // two request counters
+    const int64_t *zero_count = (const int64_t *)(misc + 14);
+    int64_t steal_waves = 2048;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            steal_waves = (int64_t)cus * 8;
+    }
     if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
     // per-location step counts reuse the hit array, dead once locations are compacted
     uint32_t *steps = g_prof_on ? (uint32_t *)hk : nullptr;
 
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)misc, 64, 0u);
     {
         const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
         timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk); });
@@ -1323,8 +1444,8 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
     auto run_pass = [&](const uint32_t *ridx, int64_t list_len, int NSp, int Kcap, int final_pass) -> int {
         const int Kp = std::min(Kmax, Kcap);
         // lane-per-location tile: reads up to LANE_LMAX bases with limits up to LANE_KMAX
-        const int lane_L = std::min(maxL, LANE_LMAX), lane_K = std::min(Kp, LANE_KMAX);
-        const bool all_lane = maxL <= LANE_LMAX && Kp <= LANE_KMAX;
+        const int lane_L = std::min(maxL, lane_lmax), lane_K = std::min(Kp, LANE_KMAX);
+        const bool all_lane = !batched && maxL <= lane_lmax && Kp <= LANE_KMAX;
         const int RW = (std::max(lane_L, 1) + 15) / 16 + 1;
         const int TW = (std::max(lane_L, 1) + lane_K + 15) / 16 + 1;
         const int kmax_t = lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63);
@@ -1394,34 +1515,82 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
                 if (!all_lane) {
                     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)route_cnt, 4, 0u);
                     timed("route", st, [&] { hipLaunchKernelGGL(k_route, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, cread, lengths, ps, rule,
-                                       ncand, LANE_LMAX, LANE_KMAX, short_list, long_list, route_cnt); });
+                                       ncand, lane_lmax, LANE_KMAX, short_list, long_list, route_cnt); });
                     slist = short_list;
                     nshort = (const int64_t *)route_cnt;
                 }
                 VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, ncand,
-                              rule, RW, TW, dcap, steps, slist, nshort};
-                const unsigned vb = (unsigned)((total + 63) / 64);
-                timed("verify", st, [&] {
-                    if (kmax_t == 15)
-                        hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), lds, st, va);
-                    else if (kmax_t == 31)
-                        hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), lds, st, va);
-                    else
-                        hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
-                });
-                if (!all_lane) {
-                    WaveVerifyArgs wa{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
-                                      long_list, (const int64_t *)(route_cnt + 1), rule, RWL, TWL, Kp, dcap, steps,
-                                      nullptr, 1};
-                    const unsigned wb = (unsigned)std::min<int64_t>(total, 8192);
-                    timed("verify_wave", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wa); });
+                              rule, RW, TW, dcap, vlim, steps, slist, nshort};
+                // final pass: long locations are verified on request, with the exact limit
+                const int64_t *nlong = (const int64_t *)(route_cnt + 1);
+                if (final_pass && !all_lane) {
+                    timed("mark", st, [&] { hipLaunchKernelGGL(k_mark_unverified, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, long_list, nlong, dcap, vlim, steps); });
+                    nlong = zero_count;
+                }
+                WaveVerifyArgs wa{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
+                                  long_list, nlong, rule, RWL, TWL, Kp, dcap, vlim, steps, nullptr, 1, nullptr};
+                if (batched) {
+                    // one persistent work-stealing launch for both tiles
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 4, 0u);
+                    const int nwaves = (int)std::min<int64_t>(std::max<int64_t>((total + 63) / 64, 1), steal_waves);
+                    StealArgs sa{va, wa, steal_next, nwaves};
+                    const size_t lds_s = std::max(lds, lds_wave);
+                    timed("verify_steal", st, [&] {
+                        if (kmax_t == 15)
+                            hipLaunchKernelGGL(k_verify_steal<15>, dim3(nwaves), dim3(64), lds_s, st, sa);
+                        else if (kmax_t == 31)
+                            hipLaunchKernelGGL(k_verify_steal<31>, dim3(nwaves), dim3(64), lds_s, st, sa);
+                        else
+                            hipLaunchKernelGGL(k_verify_steal<63>, dim3(nwaves), dim3(64), lds_s, st, sa);
+                    });
+                } else {
+                    const unsigned vb = (unsigned)((total + 63) / 64);
+                    timed("verify", st, [&] {
+                        if (kmax_t == 15)
+                            hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), lds, st, va);
+                        else if (kmax_t == 31)
+                            hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), lds, st, va);
+                        else
+                            hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
+                    });
+                    if (!all_lane && !final_pass) {
+                        const unsigned wb = (unsigned)std::min<int64_t>(total, 8192);
+                        timed("verify_wave", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wa); });
+                    }
                 }
             }
-            ReplayArgs ra{probe, key_c, mask_c, dcap, coff, ccount, bmin, scored, lengths, ps, rule, sh,
-                          pending_out, npending_out, pos, strand, dist, second, call};
-            {
-                const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
-                timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rb), dim3(256), 0, st, ra); });
+            ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
+                          pending_out, npending_out, nullptr, nullptr, req_loc, req_lim, req_list[0], nreq,
+                          pos, strand, dist, second, call};
+            const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)nreq, 2, 0u);
+            timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rb), dim3(256), 0, st, ra); });
+            if (final_pass && !all_lane) {
+                // verify what the replay asked for, replay those reads, until nothing is asked
+                for (int it = 0;; it++) {
+                    unsigned long long nq = 0;
+                    HIP_OK(hipMemcpyAsync(&nq, nreq + (it & 1), 8, hipMemcpyDeviceToHost, st));
+                    HIP_OK(hipStreamSynchronize(st));
+                    if (nq == 0) break;
+                    WaveVerifyArgs wq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
+                                      req_loc, (const int64_t *)(nreq + (it & 1)), rule, RWL, TWL, Kp, dcap, vlim, steps,
+                                      batched ? steal_next : nullptr, 1, req_lim};
+                    if (batched) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 2, 0u);
+                    const unsigned wb = (unsigned)std::min<int64_t>((int64_t)nq, steal_waves);
+                    timed("verify_request", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wq); });
+                    ReplayArgs rq = ra;
+                    rq.rlist = req_list[it & 1];
+                    rq.rlist_n = nreq + (it & 1);
+                    rq.req_read = req_list[(it + 1) & 1];
+                    rq.nreq = nreq + ((it + 1) & 1);
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(nreq + ((it + 1) & 1)), 2, 0u);
+                    const unsigned rqb = (unsigned)std::min<int64_t>(((int64_t)nq + 3) / 4, 8192);
+                    timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rqb), dim3(256), 0, st, rq); });
+                    if (g_prof_on) {
+                        std::lock_guard<std::mutex> g(g_prof_mu);
+                        g_ctr.requests += (int64_t)nq;
+                    }
+                }
             }
             HIP_OK(hipGetLastError());
             if (g_prof_on) {
@@ -1484,6 +1653,23 @@ extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int3
         list_len = (int64_t)np;
     }
     return SNAP_OK;
+}
+
+}  // namespace
+
+extern "C" int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
+                          int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,
+                          int32_t *second, int8_t *call, void *workspace, size_t ws_bytes, void *stream) {
+    return align_impl(ix, reads, lengths, n_reads, d_max, p, pos, strand, dist, second, call, workspace, ws_bytes,
+                      stream, false, nullptr);
+}
+
+extern "C" int snap_align_batched(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
+                                  int32_t d_max, const snap_params *p, const snap_tuning *tuning, int64_t *pos,
+                                  int8_t *strand, int32_t *dist, int32_t *second, int8_t *call, void *workspace,
+                                  size_t ws_bytes, void *stream) {
+    return align_impl(ix, reads, lengths, n_reads, d_max, p, pos, strand, dist, second, call, workspace, ws_bytes,
+                      stream, true, tuning);
 }
 
 // Seed offsets tried for a read of length L (host evaluation of the same
