@@ -231,6 +231,117 @@ def bench_batched(args, w, dev):
     gix.close()
 
 
+def bench_served(args, w, dev):
+    """Request server: saturated throughput, then Poisson arrivals at 25/50/90% of
+    it; per level the request latency (completion - submission) p50 / p99."""
+    import threading
+    import paper_1111_5572_amd as snapgpu
+    import synth
+
+    t = time.time()
+    g = w.make_genome()
+    pool = w.make_reads(g)
+    log(f"genome {len(g)} bases, read pool {pool.n} reads in {time.time() - t:.1f}s")
+    t = time.time()
+    gix = snapgpu.Index(g, w.params.seed_len)
+    log(f"index resident in {time.time() - t:.1f}s")
+    params = snapgpu.params_from(w.params)
+    srv = snapgpu.Server(gix, w.params.d_max, params, slots=4, batch_reads=1 << 16, batch_bases=160 << 20,
+                         hbm_budget=48 << 30, max_waiting=1 << 14)
+    log(f"server: {srv.stats()}")
+
+    offs = pool.offsets
+    cursor = [0]
+
+    def next_request(k):
+        i = cursor[0]
+        if i + k > pool.n:
+            i = 0
+        cursor[0] = i + k
+        return pool.bases[offs[i]:offs[i + k]], pool.lengths[i:i + k]
+
+    def run(n_req, arrivals=None, sizes=None):
+        """Submit n_req requests (open loop at `arrivals` seconds, or back to back),
+        poll them all; returns (elapsed, reads, latencies)."""
+        done = {}
+        tickets = []
+        lock = threading.Lock()
+        stop = [False]
+
+        def poller():
+            while True:
+                with lock:
+                    pend = [x for x in tickets if x[0] not in done]
+                    finished = stop[0] and not pend
+                for tk, _ in pend:
+                    r = srv.poll(tk)
+                    if r is not None:
+                        done[tk] = r[5]
+                if finished:
+                    return
+                time.sleep(0.0002)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t0 = time.perf_counter()
+        nreads = 0
+        for q in range(n_req):
+            if arrivals is not None:
+                dt = arrivals[q] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            b, l = next_request(int(sizes[q]))
+            while True:
+                try:
+                    tk = srv.submit(b, l)
+                    break
+                except snapgpu.SnapError as e:
+                    if e.code != snapgpu.SNAP_EBUSY:
+                        raise
+                    time.sleep(0.0005)
+            nreads += len(l)
+            with lock:
+                tickets.append((tk, len(l)))
+        with lock:
+            stop[0] = True
+        th.join()
+        elapsed = time.perf_counter() - t0
+        lat = np.array([done[tk][2] - done[tk][0] for tk, _ in tickets])
+        return elapsed, nreads, lat
+
+    rng_sizes = lambda n, seed: synth.arrivals(n, seed, 1.0)[1]
+    nq = args.steps * 100
+    run(max(20, nq // 10), sizes=rng_sizes(max(20, nq // 10), 104))   # warm-up
+    el, nr, lat = run(nq, sizes=rng_sizes(nq, 105))
+    sat = nr / el
+    log(f"saturated: {nq} requests, {nr} reads in {el:.2f}s = {sat:,.0f} reads/s; p50 {np.median(lat)*1e3:.1f} ms")
+    levels = {}
+    for load in (0.25, 0.5, 0.9):
+        sizes = rng_sizes(nq, 106)
+        rate = load * sat / float(np.mean(sizes))
+        arr, _ = synth.arrivals(nq, 107, rate)
+        el, nr, lat = run(nq, arrivals=arr, sizes=sizes)
+        levels[f"{int(load * 100)}%"] = {"offered_reads_per_s": round(load * sat, 1),
+                                         "achieved_reads_per_s": round(nr / el, 1),
+                                         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                                         "requests": nq}
+        log(f"load {load:.0%}: {levels[f'{int(load * 100)}%']}")
+    st = srv.stats()
+    srv.close()
+    gix.close()
+    line = {
+        "metric": "reads aligned/s", "value": round(sat, 1), "unit": "reads/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic (seeded genome and simulated reads; no real data)",
+        "config": {"workload": "served", "genome_bases": len(g), "read_pool": pool.n,
+                   "request_reads": "floor(10^(4u))", "read_len": "100 bp-10 kb log-uniform",
+                   "slots": st["slots"], "slot_device_bytes": st["slot_device_bytes"]},
+        "latency": levels, "server": st, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +373,8 @@ def main():
     snapgpu.lib()
     if args.workload == "batched":
         return bench_batched(args, w, dev)
+    if args.workload == "served":
+        return bench_served(args, w, dev)
 
     t = time.time()
     g = w.make_genome()

@@ -184,6 +184,75 @@ int snap_align_batched(const snap_index *ix, const uint8_t *reads, const int32_t
                        int8_t *strand, int32_t *dist, int32_t *second, int8_t *call, void *workspace,
                        size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- server */
+
+/*
+ * Request server with continuous batching. The index stays on the device. The
+ * HBM budget is divided into slots; each slot owns a HIP stream, a slice of one
+ * device arena (reads, lengths, outputs, align workspace for up to batch_reads
+ * reads / batch_bases bases) and pinned host staging, and is driven by its own
+ * host thread. A free slot admits every waiting request that fits (oldest
+ * first), runs snap_align_batched on its stream and completes those requests, so
+ * requests arriving while other slots are busy are admitted as slots free up and
+ * their work overlaps on the device. Outputs are exactly those of snap_align on
+ * the same reads; a request's result does not depend on the others in flight.
+ */
+typedef struct snap_server snap_server;
+
+typedef struct {
+    uint64_t hbm_budget;   /* device bytes the server may hold (slots are carved from it) */
+    int32_t slots;         /* at most this many slots (fewer if the budget is smaller) */
+    int32_t max_waiting;   /* submit returns SNAP_EBUSY with this many requests waiting */
+    int64_t batch_reads;   /* per-slot capacity in reads (also the largest request) */
+    int64_t batch_bases;   /* per-slot capacity in bases (also the largest request) */
+    int32_t max_len;       /* longest read accepted */
+    int32_t d_max;         /* Table 3's maximum distance for every request of this server */
+} snap_server_config;
+
+/* Result of a completed request. Arrays are host memory owned by the server and
+ * valid until snap_server_release. Times are seconds of a monotonic host clock. */
+typedef struct {
+    int64_t n;
+    int32_t status;        /* SNAP_OK, or the error the batch failed with */
+    int32_t reserved;
+    const int64_t *pos;
+    const int8_t *strand;
+    const int32_t *dist;
+    const int32_t *second;
+    const int8_t *call;
+    double t_submit, t_start, t_done;
+} snap_result;
+
+typedef struct {
+    int64_t slots, submitted, completed, failed, batches, waiting, busy_slots;
+    uint64_t slot_device_bytes;
+} snap_server_stats_t;
+
+/* hbm_budget 8 GiB, 4 slots, 4096 waiting, 262144 reads / 256 Mi bases per slot, max_len 16384, d_max 8. */
+snap_server_config snap_server_default_config(void);
+
+/* Creates the server on the current device; p and the index must outlive it.
+ * tuning may be NULL (process-wide schedule). SNAP_ENOMEM if not even one slot fits the budget. */
+int snap_server_create(const snap_index *ix, const snap_params *p, const snap_server_config *cfg,
+                       const snap_tuning *tuning, snap_server **out);
+
+/* Queues a request (host arrays, copied before return) and returns at once with its
+ * ticket. d_max must equal the server's. SNAP_EBUSY when max_waiting requests wait;
+ * SNAP_EINVAL for a request larger than a slot or reads longer than max_len. */
+int snap_server_submit(snap_server *s, const uint8_t *reads, const int32_t *lengths, int64_t n, int32_t d_max,
+                       uint64_t *ticket);
+
+/* SNAP_OK and the result once the request completed, SNAP_EAGAIN before. */
+int snap_server_poll(snap_server *s, uint64_t ticket, snap_result *out);
+
+/* Frees a completed request's result (SNAP_EAGAIN if it has not completed). */
+int snap_server_release(snap_server *s, uint64_t ticket);
+
+int snap_server_stats(snap_server *s, snap_server_stats_t *out);
+
+/* Completes every admitted and waiting request, then frees the server. */
+int snap_server_destroy(snap_server *s);
+
 /* ------------------------------------------------------- instrumentation */
 
 /* Device time of one kernel of the path, summed over launches. */

@@ -63,6 +63,26 @@ def get_tuning() -> tuple[int, int, int, int]:
     return t.astuple()
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("max_waiting", ctypes.c_int32),
+                ("batch_reads", ctypes.c_int64), ("batch_bases", ctypes.c_int64), ("max_len", ctypes.c_int32),
+                ("d_max", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pos", ctypes.POINTER(ctypes.c_int64)), ("strand", ctypes.POINTER(ctypes.c_int8)),
+                ("dist", ctypes.POINTER(ctypes.c_int32)), ("second", ctypes.POINTER(ctypes.c_int32)),
+                ("call", ctypes.POINTER(ctypes.c_int8)), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("slots", "submitted", "completed", "failed", "batches", "waiting", "busy_slots")] + \
+               [("slot_device_bytes", ctypes.c_uint64)]
+
+
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "second_pass_reads", "requests")]
@@ -109,6 +129,21 @@ def lib():
         L.snap_align_batched.argtypes = [P, P, P, i64, i32, ctypes.POINTER(Params), ctypes.POINTER(Tuning),
                                          P, P, P, P, P, P, sz, P]
         L.snap_align_batched.restype = ctypes.c_int
+        L.snap_server_default_config.argtypes = []
+        L.snap_server_default_config.restype = ServerConfig
+        L.snap_server_create.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(ServerConfig),
+                                         ctypes.POINTER(Tuning), ctypes.POINTER(P)]
+        L.snap_server_create.restype = ctypes.c_int
+        L.snap_server_submit.argtypes = [P, P, P, i64, i32, ctypes.POINTER(u64)]
+        L.snap_server_submit.restype = ctypes.c_int
+        L.snap_server_poll.argtypes = [P, u64, ctypes.POINTER(Result)]
+        L.snap_server_poll.restype = ctypes.c_int
+        L.snap_server_release.argtypes = [P, u64]
+        L.snap_server_release.restype = ctypes.c_int
+        L.snap_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+        L.snap_server_stats.restype = ctypes.c_int
+        L.snap_server_destroy.argtypes = [P]
+        L.snap_server_destroy.restype = ctypes.c_int
         L.snap_debug_copy.argtypes = [P, P, u64, P]
         L.snap_debug_copy.restype = ctypes.c_int
         _lib = L
@@ -264,6 +299,71 @@ def debug_seed_offsets(L: int, s: int, n: int) -> list[int]:
     out = np.zeros(64, np.int32)
     k = lib().snap_debug_seed_offsets(L, s, n, out.ctypes.data)
     return [int(v) for v in out[:k]]
+
+
+def server_config(**kw) -> ServerConfig:
+    c = lib().snap_server_default_config()
+    for k, v in kw.items():
+        setattr(c, k, int(v))
+    return c
+
+
+class Server:
+    """snap_server: continuous-batching request server (host arrays in and out)."""
+
+    def __init__(self, index: Index, d_max: int, params: Params | None = None, tuning=None, **cfg):
+        self.index = index
+        self.params = params or default_params()
+        self.cfg = server_config(d_max=d_max, **cfg)
+        tp = None
+        if tuning is not None:
+            tp = ctypes.byref(Tuning(*tuning) if isinstance(tuning, tuple) else tuning)
+        h = ctypes.c_void_p()
+        _check(lib().snap_server_create(index.handle, ctypes.byref(self.params), ctypes.byref(self.cfg), tp,
+                                        ctypes.byref(h)), "snap_server_create")
+        self._h = h
+
+    def submit(self, bases: np.ndarray, lengths: np.ndarray) -> int:
+        """Queue a request; returns its ticket (raises SnapError, e.g. SNAP_EBUSY)."""
+        bases = np.ascontiguousarray(bases, dtype=np.uint8)
+        lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+        t = ctypes.c_uint64()
+        _check(lib().snap_server_submit(self._h, bases.ctypes.data, lengths.ctypes.data, lengths.shape[0],
+                                        self.cfg.d_max, ctypes.byref(t)), "snap_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int, release: bool = True):
+        """None while pending; else (pos, strand, dist, second, call, (t_submit, t_start, t_done))."""
+        r = Result()
+        code = lib().snap_server_poll(self._h, ticket, ctypes.byref(r))
+        if code == SNAP_EAGAIN:
+            return None
+        _check(code, "snap_server_poll")
+        _check(r.status, "server request")
+        n = int(r.n)
+        arrs = tuple(np.ctypeslib.as_array(p, shape=(n,)).copy() if n else np.zeros(0, dt)
+                     for p, dt in ((r.pos, np.int64), (r.strand, np.int8), (r.dist, np.int32),
+                                   (r.second, np.int32), (r.call, np.int8)))
+        times = (float(r.t_submit), float(r.t_start), float(r.t_done))
+        if release:
+            _check(lib().snap_server_release(self._h, ticket), "snap_server_release")
+        return arrs + (times,)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().snap_server_stats(self._h, ctypes.byref(st)), "snap_server_stats")
+        return {n: int(getattr(st, n)) for n, _ in st._fields_}
+
+    def close(self):
+        if self._h:
+            lib().snap_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_begin():

@@ -87,4 +87,11 @@ BATCHED = Workload(
     params=Params(d_max=8, d_max_pct=8),
     notes="5M reads, log-uniform 100 bp-10 kb; <=300 bp 1% error, longer 5% (half indels); d_max=ceil(0.08 L)")
 
-WORKLOADS = {w.name: w for w in (TINY, MID, HUMAN, BATCHED)}
+SERVED = Workload(
+    name="served", genome_len=3_100_000_000, genome_seed=2, genome_kind="repeats", n_frac=0.01,
+    n_reads=1_000_000, read_seed=104,
+    reads=BATCHED.reads,
+    params=BATCHED.params,
+    notes="requests of floor(10^(4u)) reads drawn from a pool with the batched length/error mix; Poisson arrivals")
+
+WORKLOADS = {w.name: w for w in (TINY, MID, HUMAN, BATCHED, SERVED)}

@@ -1,0 +1,126 @@
+"""The request server (continuous batching): every request's result equals the
+same reads aligned alone, whatever else is in flight; queue-full and invalid
+requests are refused without disturbing the rest; destroy drains the queue."""
+import time
+
+import numpy as np
+import pytest
+
+from helpers import compare, gpu_align, oracle_align, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def snapgpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1111_5572_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def world(synth_mod):
+    from synth.workloads import BATCHED
+    w = BATCHED.scaled(genome_len=2_000_000, n_reads=3000)
+    g = w.make_genome()
+    reads = w.make_reads(g)
+    return w, g, reads
+
+
+def split_requests(reads, sizes):
+    out, i = [], 0
+    for k in sizes:
+        idx = np.arange(i, min(i + k, reads.n))
+        if len(idx) == 0:
+            break
+        out.append(reads.subset(idx))
+        i += k
+    return out
+
+
+def drain(srv, tickets, timeout=300):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                r = srv.poll(t)
+                if r is not None:
+                    res[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(res)} of {len(tickets)} requests completed")
+        time.sleep(0.001)
+    return res
+
+
+def test_results_same_alone_and_in_mix(snapgpu, oracle_mod, world):
+    w, g, reads = world
+    gix = snapgpu.Index(g, 20)
+    gp = snapgpu.params_from(w.params)
+    rng = np.random.default_rng(5)
+    sizes = [int(x) for x in np.floor(10 ** (rng.random(60) * 2.5)).astype(int) + 1]
+    reqs = split_requests(reads, sizes)
+    say(f"[server] {len(reqs)} requests, {sum(r.n for r in reqs)} reads")
+    srv = snapgpu.Server(gix, w.params.d_max, gp, slots=3, batch_reads=400, batch_bases=1_500_000,
+                         hbm_budget=6 << 30, max_waiting=1000)
+    tickets = [srv.submit(r.bases, r.lengths) for r in reqs]
+    res = drain(srv, tickets)
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["batches"] < len(reqs)   # requests shared batches
+    for t, r in zip(tickets, reqs):
+        alone = gpu_align(snapgpu, gix, r, w.params.d_max, gp)
+        got = res[t][:5]
+        nbad, rep = compare(got, alone, r, f"request {t} in mix vs alone")
+        assert nbad == 0, rep
+        assert res[t][5][0] <= res[t][5][1] <= res[t][5][2]
+    # and a sample against the oracle
+    oix = oracle_mod.Index(g, 20)
+    for t, r in list(zip(tickets, reqs))[:6]:
+        nbad, rep = compare(res[t][:5], oracle_align(oracle_mod, oix, r, w.params), r, f"request {t} vs oracle")
+        assert nbad == 0, rep
+    oix.close()
+    srv.close()
+    gix.close()
+
+
+def test_queue_full_and_invalid_requests(snapgpu, world):
+    w, g, reads = world
+    gix = snapgpu.Index(g, 20)
+    gp = snapgpu.params_from(w.params)
+    srv = snapgpu.Server(gix, w.params.d_max, gp, slots=1, batch_reads=300, batch_bases=1_000_000,
+                         hbm_budget=4 << 30, max_waiting=3)
+    reqs = split_requests(reads, [50] * 30)
+    tickets, busy = [], 0
+    for r in reqs:
+        try:
+            tickets.append(srv.submit(r.bases, r.lengths))
+        except snapgpu.SnapError as e:
+            assert e.code == snapgpu.SNAP_EBUSY
+            busy += 1
+    assert busy > 0 and tickets
+    too_big = reads.subset(np.arange(400))
+    with pytest.raises(snapgpu.SnapError) as ei:
+        srv.submit(too_big.bases, too_big.lengths)
+    assert ei.value.code == snapgpu.SNAP_EINVAL
+    res = drain(srv, tickets)
+    assert len(res) == len(tickets)
+    srv.close()
+    gix.close()
+
+
+def test_destroy_drains_waiting_requests(snapgpu, world):
+    w, g, reads = world
+    gix = snapgpu.Index(g, 20)
+    gp = snapgpu.params_from(w.params)
+    srv = snapgpu.Server(gix, w.params.d_max, gp, slots=2, batch_reads=200, batch_bases=800_000,
+                         hbm_budget=4 << 30, max_waiting=100)
+    reqs = split_requests(reads, [40] * 20)
+    for r in reqs:
+        srv.submit(r.bases, r.lengths)
+    srv.close()   # returns after every request completed
+    gix.close()
