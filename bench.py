@@ -392,8 +392,16 @@ def main():
     ln = torch.from_numpy(reads.lengths).to(dev)
     params = snapgpu.params_from(w.params)
     max_len = int(reads.lengths.max())
-    wb = snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), max_len, w.params.d_max, params)
+    # a generous workspace: more reads per internal pass, fewer waits (outputs do not change)
+    wb = 4 * snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), max_len, w.params.d_max, params)
     ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    tune_info = None
+    if not args.no_autotune:
+        from paper_1111_5572_amd import autotune
+        tune_info = autotune.tune(gix, rb, ln, w.params.d_max, params, batched=False,
+                                  sample_reads=min(reads.n, 1_000_000), table_path=None, log=log)
+        snapgpu.set_tuning(*tune_info["tuning"])
+        log(f"autotuned schedule {tuple(tune_info['tuning'])}")
     out = snapgpu.align(gix, rb, ln, w.params.d_max, params, workspace=ws, max_len=max_len)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -505,6 +513,7 @@ def main():
         "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
         "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
+        "schedule": tune_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -150,18 +150,21 @@ int32_t snap_max_limit(void);
 
 /*
  * Output-invariant schedule of snap_align (process-wide). A first pass probes
- * only the first pass1_seeds seed slots of every read and verifies locations
- * with limit pass1_limit; Algorithm 1 is replayed on that, and a read is settled
+ * only the first pass1_seeds seed slots of every read and verifies locations with
+ * limit pass1_limit; Algorithm 1 is replayed on that, and a read is settled
  * whenever the replay never needs a seed or a distance beyond what the pass
- * computed. The reads left over go through a pass with every seed and limit
- * pass2_limit (when set), and what is still left through a pass with every seed
- * and the full limit d_max(L) + c - 1. 0 in a field means "no cap" (a single
- * complete pass when all are 0). Outputs never depend on these values.
+ * computed. The reads left over go through a final pass with every seed: there,
+ * short reads' locations are verified with limit final_limit first, and the reads
+ * whose replay needs more are verified again with the full limit
+ * d_max(L) + c - 1; long reads' locations are verified when the replay asks for
+ * them, with exactly the limit it uses. 0 in a field means "no cap" (no first
+ * pass when pass1_seeds and pass1_limit are both 0). Outputs never depend on
+ * these values.
  */
 typedef struct {
     int32_t pass1_seeds;
     int32_t pass1_limit;
-    int32_t pass2_limit;
+    int32_t final_limit;
     int32_t lane_max_len;   /* verify tile: reads up to this length (and limits up to 63) get one lane
                                per location, longer ones a wave per location; 0 = 512 (the maximum) */
 } snap_tuning;

@@ -45,15 +45,15 @@ class KernelTime(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "pass2_limit", "lane_max_len")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "final_limit", "lane_max_len")]
 
     def astuple(self):
-        return (int(self.pass1_seeds), int(self.pass1_limit), int(self.pass2_limit), int(self.lane_max_len))
+        return (int(self.pass1_seeds), int(self.pass1_limit), int(self.final_limit), int(self.lane_max_len))
 
 
-def set_tuning(pass1_seeds: int, pass1_limit: int, pass2_limit: int = 0, lane_max_len: int = 0):
-    """Output-invariant pass schedule and verify tile bound (see snap_set_tuning); 0 = default."""
-    _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, pass2_limit, lane_max_len))),
+def set_tuning(pass1_seeds: int, pass1_limit: int, final_limit: int = 0, lane_max_len: int = 0):
+    """Output-invariant pass schedule and verify tile bound (see snap_set_tuning); 0 = no cap."""
+    _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, final_limit, lane_max_len))),
            "snap_set_tuning")
 
 

@@ -336,31 +336,65 @@ struct GatherArgs {
     uint64_t *hk;      // per hit: ((p << 1 | strand) << 5) | seed slot, or HIT_NONE
 };
 
-// Algorithm 1's vote loop, one thread per (read, seed slot): a forward hit q of
-// the seed at offset o votes for (+, q - o), a reverse hit for (-, q - (L - o - s));
-// locations outside [0, G - L] are dropped.
-__global__ void k_gather(GatherArgs a) {
+// Algorithm 1's vote loop, one wave per read. Lane i holds seed slot i's probe
+// record; a wave prefix sum places each slot's hits in the read's region; the lanes
+// then take 64 hits at a time (coalesced position reads and hit writes). A forward
+// hit q of the seed at offset o votes for (+, q - o), a reverse hit for
+// (-, q - (L - o - s)); locations outside [0, G - L] are dropped.
+__global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     const int NS = a.ps.NS;
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= a.ps.nr * NS) return;
-    const int64_t r = item / NS;
-    const int i = (int)(item % NS);
-    const ProbeRec p = a.pr[item];
-    if (p.status != ST_OK || p.nf + p.nr == 0) return;
-    int64_t off = a.hoff[r];
-    for (int i2 = 0; i2 < i; i2++) {
-        const ProbeRec &q = a.pr[r * NS + i2];
-        if (q.status == ST_OK) off += q.nf + q.nr;
-    }
-    const int64_t L = a.len[gid(a.ps, r)];
-    for (uint32_t j = 0; j < p.nf; j++) {
-        const int64_t pp = (int64_t)a.positions[p.off_f + j] - p.o;
-        a.hk[off + j] = (pp >= 0 && pp + L <= (int64_t)a.G) ? ((((uint64_t)pp << 1)) << 5) | (uint64_t)i : HIT_NONE;
-    }
-    off += p.nf;
-    for (uint32_t j = 0; j < p.nr; j++) {
-        const int64_t pp = (int64_t)a.positions[p.off_r + j] - (L - p.o - a.s);
-        a.hk[off + j] = (pp >= 0 && pp + L <= (int64_t)a.G) ? ((((uint64_t)pp << 1) | 1) << 5) | (uint64_t)i : HIT_NONE;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < a.ps.nr; r += nwaves) {
+        const int64_t base = a.hoff[r];
+        const int64_t L = a.len[gid(a.ps, r)];
+        uint32_t cnt = 0, nf = 0, o = 0;
+        uint64_t offf = 0, offr = 0;
+        if (lane < NS) {
+            const ProbeRec p = a.pr[r * NS + lane];
+            if (p.status == ST_OK) {
+                cnt = p.nf + p.nr;
+                nf = p.nf;
+                o = p.o;
+                offf = p.off_f;
+                offr = p.off_r;
+            }
+        }
+        uint32_t incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += v;
+        }
+        const uint32_t start = incl - cnt;
+        const uint32_t H = __shfl(incl, 63, 64);
+        // chunks of 64 hits, every lane taking part in the shuffles (a shuffle reads
+        // nothing useful from a lane that is switched off)
+        for (uint32_t j0 = 0; j0 < H; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            // the slot whose range holds hit j
+            int slot = 0;
+            for (int i = 1; i < NS; i++) {
+                const uint32_t si = __shfl(start, i, 64), ci = __shfl(cnt, i, 64);
+                if (si <= j && ci > 0) slot = i;
+            }
+            const uint32_t k = j - __shfl(start, slot, 64);
+            const uint32_t snf = __shfl(nf, slot, 64);
+            const int64_t so = __shfl(o, slot, 64);
+            const uint64_t offF = ((uint64_t)__shfl((uint32_t)(offf >> 32), slot, 64) << 32) | __shfl((uint32_t)offf, slot, 64);
+            const uint64_t offR = ((uint64_t)__shfl((uint32_t)(offr >> 32), slot, 64) << 32) | __shfl((uint32_t)offr, slot, 64);
+            if (j < H) {
+                uint64_t h;
+                if (k < snf) {
+                    const int64_t pp = (int64_t)a.positions[offF + k] - so;
+                    h = (pp >= 0 && pp + L <= (int64_t)a.G) ? (((uint64_t)pp << 1) << 5) | (uint64_t)slot : HIT_NONE;
+                } else {
+                    const int64_t pp = (int64_t)a.positions[offR + (k - snf)] - (L - so - a.s);
+                    h = (pp >= 0 && pp + L <= (int64_t)a.G) ? ((((uint64_t)pp << 1) | 1) << 5) | (uint64_t)slot : HIT_NONE;
+                }
+                a.hk[base + j] = h;
+            }
+        }
     }
 }
 
@@ -441,26 +475,27 @@ __global__ __launch_bounds__(256) void k_dedupe_light(DedupeArgs a) {
 // place), then the same merge of equal locations, 256 hits at a time.
 // Reads with more hits than fit in LDS sort in place in a global scratch region
 // of their own (the same code with IN_LDS false).
-template <bool IN_LDS>
-__global__ __launch_bounds__(256) void k_dedupe_heavy(DedupeArgs a, uint64_t *gscratch, uint32_t cape) {
+// NT threads per read; the kernel takes reads with lo < H <= hi hits.
+template <bool IN_LDS, int NT>
+__global__ __launch_bounds__(NT) void k_dedupe_heavy(DedupeArgs a, uint64_t *gscratch, uint32_t lo_h, uint32_t hi_h) {
     extern __shared__ uint64_t lds_keys[];
-    __shared__ uint32_t wcnt[4];
+    __shared__ uint32_t wcnt[NT / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int64_t r = blockIdx.x; r < a.nr; r += gridDim.x) {
         const uint32_t H = a.hits[r];
-        if (H <= 64 || (IN_LDS ? H > cape : H <= cape)) continue;
+        if (H <= lo_h || H > hi_h) continue;
         const int64_t base = a.hoff[r];
         uint64_t *sk = IN_LDS ? lds_keys : gscratch + base;
         uint32_t N = 1;
         while (N < H) N <<= 1;
-        for (uint32_t i = tid; i < H; i += 256) {
+        for (uint32_t i = tid; i < H; i += NT) {
             sk[i] = a.hk[base + i];
             a.slot_read[base + i] = (uint32_t)r;
         }
         __syncthreads();
         for (uint32_t k = 2; k <= N; k <<= 1) {
             const uint32_t half = k >> 1;
-            for (uint32_t i = tid; i < N / 2; i += 256) {
+            for (uint32_t i = tid; i < N / 2; i += NT) {
                 const uint32_t blk = i / half, off = i % half;
                 const uint32_t lo = blk * k + off, hi = blk * k + k - 1 - off;
                 if (hi < H) {
@@ -470,7 +505,7 @@ __global__ __launch_bounds__(256) void k_dedupe_heavy(DedupeArgs a, uint64_t *gs
             }
             __syncthreads();
             for (uint32_t j = k >> 2; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < N / 2; i += 256) {
+                for (uint32_t i = tid; i < N / 2; i += NT) {
                     const uint32_t lo = (i / j) * 2 * j + (i % j), hi = lo + j;
                     if (hi < H) {
                         const uint64_t x = sk[lo], y = sk[hi];
@@ -481,7 +516,7 @@ __global__ __launch_bounds__(256) void k_dedupe_heavy(DedupeArgs a, uint64_t *gs
             }
         }
         uint32_t run = 0;
-        for (uint32_t c0 = 0; c0 < H; c0 += 256) {
+        for (uint32_t c0 = 0; c0 < H; c0 += NT) {
             const uint32_t i = c0 + tid;
             bool first = false;
             uint32_t acc = 0;
@@ -496,7 +531,7 @@ __global__ __launch_bounds__(256) void k_dedupe_heavy(DedupeArgs a, uint64_t *gs
             if (lane == 0) wcnt[w] = (uint32_t)__popcll(fb);
             __syncthreads();
             uint32_t before = run, tot = 0;
-            for (int q = 0; q < 4; q++) {
+            for (int q = 0; q < NT / 64; q++) {
                 if (q < w) before += wcnt[q];
                 tot += wcnt[q];
             }
@@ -576,17 +611,51 @@ struct Stage {
 
 // Extend a diagonal: from read row i on diagonal d (text column i + d), advance
 // while read and text bases are equal (N equals nothing), 16 bases per step.
+// HAS_N false: neither the read nor the window holds an N, so the N masks are skipped.
+template <bool HAS_N>
 __device__ inline int slide(const Stage &st, int i, int d, int L, int Tn) {
     for (;;) {
         const int j = i + d;
         const int rem = min(L - i, Tn - j);
         if (rem <= 0) return i;
         const uint32_t x = st.r16(i) ^ st.t16(j);
-        uint32_t m = ((x | (x >> 1)) & 0x55555555u) | st.rn16(i) | st.tn16(j);
+        uint32_t m = (x | (x >> 1)) & 0x55555555u;
+        if (HAS_N) m |= st.rn16(i) | st.tn16(j);
         if (rem < 16) m |= 0xFFFFFFFFu << (2 * rem);
         if (m == 0) { i += 16; continue; }
         return i + (int)(__builtin_ctz(m) >> 1);
     }
+}
+
+// Furthest-reaching rows per diagonal for e = 0, 1, ..., K (the rows of the previous
+// round kept in LDS, updated in place left to right). Returns D if D <= K, else K + 1.
+template <int KMAX, bool HAS_N>
+__device__ inline int lv_lane(const Stage &st, int L, int Tn, int K, uint32_t &nsteps) {
+    constexpr int NEG = -30000;
+    const int lane = st.lane;
+    const int i0 = slide<HAS_N>(st, 0, 0, L, Tn);
+    if (i0 >= L) return 0;
+    for (int t = 0; t < 2 * KMAX + 3; t++) st.FR[t * 64 + lane] = (int16_t)NEG;
+    st.FR[(KMAX + 1) * 64 + lane] = (int16_t)i0;
+    for (int e = 1; e <= K; e++) {
+        int left = NEG;   // previous round's value on diagonal d - 1
+        for (int d = -e; d <= e; d++) {
+            const int idx = d + KMAX + 1;
+            const int od = st.FR[idx * 64 + lane], orr = st.FR[(idx + 1) * 64 + lane];
+            int i = max(left, max(od, orr) + 1);
+            left = od;
+            i = min(i, min(L, Tn - d));
+            if (i >= max(0, -d)) {
+                nsteps++;
+                i = slide<HAS_N>(st, i, d, L, Tn);
+                if (i >= L) return e;
+            } else {
+                i = NEG;
+            }
+            st.FR[idx * 64 + lane] = (int16_t)i;
+        }
+    }
+    return K + 1;
 }
 
 // Bounded edit distance (Section 3.2): D = min over j of Lev(read', text[0, j)),
@@ -614,6 +683,7 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
     const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
 
     const int nrw = (L + 15) >> 4;
+    uint32_t anyn = 0;
     for (int w = 0; w < nrw; w++) {
         uint32_t c, n;
         if (strand == 0) {
@@ -624,6 +694,7 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
             c = rc16(ext_code16(a.rcode, x));
             n = __builtin_bitreverse32(ext_mask16(a.rmask, x)) >> 16;
         }
+        anyn |= n;
         st.RC[w * 64 + lane] = c;
         st.RN[w * 64 + lane] = spread16(n);
     }
@@ -631,43 +702,16 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
     st.RN[nrw * 64 + lane] = 0;
     const int ntw = (Tn + 15) >> 4;
     for (int w = 0; w < ntw; w++) {
+        const uint32_t n = ext_mask16(a.gmask, p + 16 * w);
+        anyn |= n;
         st.TC[w * 64 + lane] = ext_code16(a.gcode, p + 16 * w);
-        st.TN[w * 64 + lane] = spread16(ext_mask16(a.gmask, p + 16 * w));
+        st.TN[w * 64 + lane] = spread16(n);
     }
     st.TC[ntw * 64 + lane] = 0;
     st.TN[ntw * 64 + lane] = 0;
 
-    constexpr int NEG = -30000;
-    int D = K + 1;
     uint32_t nsteps = 1;
-    const int i0 = slide(st, 0, 0, L, Tn);
-    if (i0 >= L) {
-        D = 0;
-    } else {
-        for (int t = 0; t < 2 * KMAX + 3; t++) st.FR[t * 64 + lane] = (int16_t)NEG;
-        st.FR[(KMAX + 1) * 64 + lane] = (int16_t)i0;
-        for (int e = 1; e <= K; e++) {
-            int left = NEG;   // previous round's value on diagonal d - 1
-            bool done = false;
-            for (int d = -e; d <= e; d++) {
-                const int idx = d + KMAX + 1;
-                const int od = st.FR[idx * 64 + lane], orr = st.FR[(idx + 1) * 64 + lane];
-                int i = max(left, max(od, orr) + 1);
-                left = od;
-                i = min(i, min(L, Tn - d));
-                if (i >= max(0, -d)) {
-                    nsteps++;
-                    i = slide(st, i, d, L, Tn);
-                    if (i >= L) done = true;
-                } else {
-                    i = NEG;
-                }
-                st.FR[idx * 64 + lane] = (int16_t)i;
-                if (done) break;
-            }
-            if (done) { D = e; break; }
-        }
-    }
+    const int D = anyn ? lv_lane<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane<KMAX, false>(st, L, Tn, K, nsteps);
     a.dcap[k] = (uint16_t)D;
     a.vlim[k] = (int16_t)K;
     if (a.steps) a.steps[k] = nsteps;
@@ -867,6 +911,24 @@ __global__ __launch_bounds__(64) void k_verify_steal(StealArgs a) {
     }
 }
 
+// Every location of the listed reads, appended to a verify list (one wave per read).
+__global__ __launch_bounds__(256) void k_expand_reads(const uint32_t *reads, const unsigned long long *n_ptr,
+                                                      const int64_t *coff, const uint32_t *count, uint32_t *out,
+                                                      unsigned long long *nout) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t n = (int64_t)*n_ptr;
+    for (int64_t q = wave; q < n; q += nwaves) {
+        const uint32_t r = reads[q];
+        const int64_t base = coff[r], C = count[r];
+        unsigned long long at = 0;
+        if (lane == 0) at = atomicAdd(nout, (unsigned long long)C);
+        at = __shfl(at, 0, 64);
+        for (int64_t k = lane; k < C; k += 64) out[at + k] = (uint32_t)(base + k);
+    }
+}
+
 // Locations left for verification on request: capped distance unknown above -1.
 __global__ void k_mark_unverified(const uint32_t *list, const int64_t *n_ptr, uint16_t *dcap, int16_t *vlim,
                                   uint32_t *steps) {
@@ -945,6 +1007,9 @@ struct ReplayArgs {
     int32_t *req_lim;           //   the limit to verify it with,
     uint32_t *req_read;         //   and the read (replayed again once it is verified)
     unsigned long long *nreq;
+    uint32_t *full_read;        // final pass, short reads: reads whose locations are re-verified at K
+    unsigned long long *nfull;
+    int32_t lane_lmax;          // reads up to this length (limit <= 63) are verified one lane per location
     int64_t *pos;
     int8_t *strand;
     int32_t *dist, *second;
@@ -969,6 +1034,40 @@ __device__ inline int d_limit(const ReadState &st, int dmax, int c) {
     if (st.d_best > dmax) return dmax + c - 1;
     if (st.d_second >= st.d_best + c) return st.d_best + c - 1;
     return st.d_best - 1;
+}
+
+// State update for a result at a location whose bucket now holds (vd, vp) (shared
+// by both replay paths).
+__device__ inline void state_update(ReadState &st, int64_t rep, int vd, int64_t vp, int s) {
+    if (st.best_rep == rep) {
+        st.d_best = vd;
+        st.best_p = vp;
+    } else if (st.best_rep < 0 || lex_less(vd, vp, s, st.d_best, st.best_p, st.best_s)) {
+        st.d_second = st.best_rep < 0 ? DINF : st.d_best;
+        st.d_best = vd;
+        st.best_p = vp;
+        st.best_s = s;
+        st.best_rep = rep;
+    } else if (vd < st.d_second) {
+        st.d_second = vd;
+    }
+}
+
+// Reads with at most 64 locations: location k lives in lane k's registers (key,
+// seed mask, capped distance, verified limit, scored flag, bucket minimum when k is
+// its bucket's representative), so the replay runs on shuffles and ballots.
+__device__ inline void light_record(int j, int d, ReadState &st, uint64_t key, int rep, uint64_t &bmin, int lane) {
+    const uint32_t klo = __shfl((unsigned)(uint32_t)key, j, 64), khi = __shfl((unsigned)(uint32_t)(key >> 32), j, 64);
+    const uint64_t kj = ((uint64_t)khi << 32) | klo;
+    const int64_t p = (int64_t)(kj >> 1);
+    const int s = (int)(kj & 1);
+    const int rj = __shfl(rep, j, 64);
+    const uint32_t blo = __shfl((unsigned)(uint32_t)bmin, rj, 64), bhi = __shfl((unsigned)(uint32_t)(bmin >> 32), rj, 64);
+    const uint64_t bv = ((uint64_t)bhi << 32) | blo;
+    const uint64_t nv0 = ((uint64_t)d << 32) | (uint64_t)p;
+    const uint64_t nv = nv0 < bv ? nv0 : bv;
+    if (lane == rj) bmin = nv;
+    state_update(st, rj, (int)(nv >> 32), (int64_t)(nv & 0xFFFFFFFFull), s);
 }
 
 // A result d <= limit at location k: merge into its bucket and update the state.
@@ -1000,21 +1099,9 @@ __device__ inline void wave_record(const ReplayArgs &a, int64_t base, int64_t k,
     const uint64_t old = a.bmin[base + j];
     const uint64_t nv = nv0 < old ? nv0 : old;
     if (lane == 0) a.bmin[base + j] = nv;
-    const int vd = (int)(nv >> 32);
-    const int64_t vp = (int64_t)(nv & 0xFFFFFFFFull);
-    if (st.best_rep == j) {
-        st.d_best = vd;
-        st.best_p = vp;
-    } else if (st.best_rep < 0 || lex_less(vd, vp, s, st.d_best, st.best_p, st.best_s)) {
-        st.d_second = st.best_rep < 0 ? DINF : st.d_best;
-        st.d_best = vd;
-        st.best_p = vp;
-        st.best_s = s;
-        st.best_rep = j;
-    } else if (vd < st.d_second) {
-        st.d_second = vd;
-    }
+    state_update(st, j, (int)(nv >> 32), (int64_t)(nv & 0xFFFFFFFFull), s);
 }
+
 
 __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
     for (int d = 32; d >= 1; d >>= 1) {
@@ -1054,10 +1141,6 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         const int NS = a.ps.NS;
         const int64_t base = a.coff[r];
         const int64_t C = a.count[r];
-        for (int64_t k = lane; k < C; k += 64) {
-            a.scored[base + k] = 0;
-            a.bmin[base + k] = ~0ull;
-        }
         ReadState st{DINF, DINF, -1, -1, -1};
         const int round0 = L / a.rule.s;
         int t = 0, call = -1;
@@ -1065,6 +1148,84 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         int64_t need_k = -1;
         int need_lim = 0;
         uint32_t prefix = 0;
+        if (C <= 64) {
+            // ---- registers: location `lane`
+            const bool have = lane < C;
+            const uint64_t key = have ? a.key[base + lane] : ~0ull;
+            const uint32_t mask = have ? a.mask[base + lane] : 0u;
+            const int dc = have ? (int)a.dcap[base + lane] : 0;
+            const int vl = have ? (int)a.vlim[base + lane] : 0;
+            const int stat = lane < NS ? (int)a.pr[r * NS + lane].status : ST_NONE;
+            bool scored = false;
+            uint64_t bmin = ~0ull;
+            // bucket representative: first location of the same strand in the run of
+            // equal buckets that ends here
+            const int64_t bk = have ? (int64_t)(key >> 1) / a.rule.bucket : -1 - lane;
+            const uint32_t bkl = __shfl((unsigned)(uint32_t)bk, (lane + 63) & 63, 64);
+            const uint32_t bkh = __shfl((unsigned)(uint32_t)((uint64_t)bk >> 32), (lane + 63) & 63, 64);
+            const int64_t bprev = (int64_t)(((uint64_t)bkh << 32) | bkl);
+            const uint64_t starts = __ballot(lane == 0 || bprev != bk);
+            const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+            const int run0 = 63 - __clzll(starts & upto);
+            const uint64_t same_s = __ballot(have && (key & 1)) ;
+            const uint64_t mine = (key & 1) ? same_s : ~same_s;
+            const uint64_t range = upto & ~((1ull << run0) - 1);
+            const int rep = __builtin_ctzll(mine & range);
+            for (int i = 0; i < NS; i++) {
+                const int status = __shfl(stat, i, 64);
+                if (status == ST_NONE) { ended = true; break; }
+                if (status == ST_N) continue;
+                looked = true;
+                if (status == ST_OVER) continue;
+                all_over = false;
+                prefix |= 1u << i;
+                if (i < round0) t++;
+                const uint32_t m = mask & prefix;
+                unsigned long long v = (have && m && !scored)
+                    ? ((unsigned long long)__builtin_popcount(m) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)lane)
+                    : 0ull;
+                v = wave_max_u64(v);
+                if (v) {
+                    const int kb = (int)(0xFFFFFFFFu - (uint32_t)(v & 0xFFFFFFFFull));
+                    const int lim = d_limit(st, dmax, c);
+                    const int res = ed_answer(__shfl(dc, kb, 64), __shfl(vl, kb, 64), lim);
+                    if (res == -2) { unresolved = true; need_k = kb; need_lim = lim; break; }
+                    if (lane == kb) scored = true;
+                    if (res >= 0) light_record(kb, res, st, key, rep, bmin, lane);
+                }
+                if (st.d_best < c && st.d_second < st.d_best + c) {
+                    call = SNAP_MULTIPLE;
+                    ended = true;
+                    break;
+                }
+                if (st.d_best < DINF && t >= st.d_best + c) {
+                    for (int lev = __builtin_popcount(prefix); lev >= 1 && !unresolved; lev--) {
+                        bool in = have && !scored && __builtin_popcount(mask & prefix) == lev;
+                        for (;;) {
+                            const int lim = d_limit(st, dmax, c);
+                            const int res = in ? ed_answer(dc, vl, lim) : -1;
+                            const uint64_t bits = __ballot(res != -1);
+                            if (!bits) break;
+                            const int j = __builtin_ctzll(bits);
+                            if ((__ballot(res == -2) >> j) & 1) {
+                                unresolved = true;
+                                need_k = j;
+                                need_lim = lim;
+                                break;
+                            }
+                            light_record(j, __shfl(res, j, 64), st, key, rep, bmin, lane);
+                            if (lane <= j) in = false;
+                        }
+                    }
+                    ended = true;
+                    break;
+                }
+            }
+        } else {
+        for (int64_t k = lane; k < C; k += 64) {
+            a.scored[base + k] = 0;
+            a.bmin[base + k] = ~0ull;
+        }
         for (int i = 0; i < NS; i++) {
             const int status = a.pr[r * NS + i].status;
             if (status == ST_NONE) { ended = true; break; }
@@ -1133,14 +1294,20 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                 break;
             }
         }
+        }   // locations in global memory
         // all slots of this pass used and the read still has seeds to try
         if (!ended && !unresolved && NS < seeds_for_length(a.rule, L) && seed_offset(a.sh, a.rule.s, L, NS) >= 0)
             unresolved = true;
         if (unresolved) {
             if (lane == 0) {
+                const bool lane_class = L <= a.lane_lmax && dmax + c - 1 <= LANE_KMAX;
                 if (!a.ps.final_pass || need_k < 0) {
                     a.pending[atomicAdd(a.npending, 1ull)] = (uint32_t)g;
+                } else if (lane_class) {
+                    // every location of the read again, with the full limit
+                    a.full_read[atomicAdd(a.nfull, 1ull)] = (uint32_t)r;
                 } else {
+                    // that location, with exactly the limit Algorithm 1 uses there
                     const unsigned long long q = atomicAdd(a.nreq, 1ull);
                     a.req_loc[q] = (uint32_t)(base + need_k);
                     a.req_lim[q] = need_lim;
@@ -1233,7 +1400,7 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     l.off_ccount = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
     l.off_coff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
     l.off_scan = o; o = align256(o + std::max(scan_tmp_bytes(R + 1), scan_tmp_bytes(n + 1)));
-    l.off_req = o; o = align256(o + 4 * sizeof(uint32_t) * (size_t)R);   // location, limit, two read lists
+    l.off_req = o; o = align256(o + 6 * sizeof(uint32_t) * (size_t)R);   // location, limit, four read lists
     const int64_t minslots = (int64_t)NS * hmax;
     if (pool_slots < minslots) pool_slots = minslots;
     l.pool_slots = pool_slots;
@@ -1282,7 +1449,7 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {4, 4, 0, 0};   // seeds and limit of stage 1, limit of stage 2, lane-tile read bound
+snap_tuning g_tune = {6, 0, 4, 0};   // stage-1 seeds and limit, final first limit, lane-tile read bound
 
 constexpr int KCAP_NONE = 1 << 20;
 
@@ -1297,7 +1464,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->pass2_limit < 0 || t->lane_max_len < 0) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -1338,7 +1505,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
-    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.pass2_limit < 0 || tune.lane_max_len < 0) return SNAP_EINVAL;
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0) return SNAP_EINVAL;
     const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
     int dev = 0, lds_max = 0;
     HIP_OK(hipGetDevice(&dev));
@@ -1405,6 +1572,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     uint32_t *req_loc = (uint32_t *)(ws + l.off_req);
     int32_t *req_lim = (int32_t *)(req_loc + R);
     uint32_t *req_list[2] = {(uint32_t *)(req_lim + R), (uint32_t *)(req_lim + R) + R};
+    uint32_t *full_list[2] = {req_list[1] + R, req_list[1] + 2 * R};
     const int64_t PS = l.pool_slots;
     char *pool = ws + l.off_pool;
     auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
@@ -1425,6 +1593,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     unsigned long long *steal_next = (unsigned long long *)(misc + 10);  // two cursors
     unsigned long long *nreq = (unsigned long long *)(misc + 12);        // two request counters
     const int64_t *zero_count = (const int64_t *)(misc + 14);
+    unsigned long long *nfull = (unsigned long long *)(misc + 16);       // two full-read counters
     int64_t steal_waves = 2048;
     {
         int cus = 0;
@@ -1450,10 +1619,12 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int TW = (std::max(lane_L, 1) + lane_K + 15) / 16 + 1;
         const int kmax_t = lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63);
         const size_t lds = (size_t)64 * 4 * (2 * RW + 2 * TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
-        // wave-per-location tile: any read, any limit
+        // wave-per-location tile: any read, any limit (the final pass verifies on
+        // request up to the full limit)
+        const int Kw = final_pass ? Kmax : Kp;
         const int RWL = (std::max(maxL, 1) + 15) / 16 + 1;
-        const int TWL = (std::max(maxL, 1) + Kp + 15) / 16 + 1;
-        const size_t lds_wave = (size_t)4 * (2 * RWL + 2 * TWL) + (size_t)8 * (2 * Kp + 3);
+        const int TWL = (std::max(maxL, 1) + Kw + 15) / 16 + 1;
+        const size_t lds_wave = (size_t)4 * (2 * RWL + 2 * TWL) + (size_t)8 * (2 * Kw + 3);
         if (lds > (size_t)lds_max || (!all_lane && lds_wave > (size_t)lds_max)) return SNAP_EINVAL;
         for (int64_t r0 = 0; r0 < list_len;) {
             int64_t nr = std::min<int64_t>(R, list_len - r0);
@@ -1487,8 +1658,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             }
             if (total > 0) {
                 GatherArgs ga{probe, ix->d.positions, ix->d.G, ix->d.s, lengths, ps, hoff, hk};
-                const int64_t gitems = nr * NSp;
-                timed("gather", st, [&] { hipLaunchKernelGGL(k_gather, dim3((unsigned)((gitems + 255) / 256)), dim3(256), 0, st, ga); });
+                const unsigned gb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
+                timed("gather", st, [&] { hipLaunchKernelGGL(k_gather, dim3(gb), dim3(256), 0, st, ga); });
             }
             DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, slot_read};
             {
@@ -1496,12 +1667,17 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 timed("dedupe_light", st, [&] { hipLaunchKernelGGL(k_dedupe_light, dim3(lb), dim3(256), 0, st, da); });
             }
             if (maxH > 64) {
-                const unsigned hb = (unsigned)std::min<int64_t>(nr, 2048);
-                uint32_t N = 1;
-                while (N < std::min(maxH, cape)) N <<= 1;
-                timed("dedupe_heavy", st, [&] { hipLaunchKernelGGL(k_dedupe_heavy<true>, dim3(hb), dim3(256), (size_t)N * 8, st, da, key_c, cape); });
-                if (maxH > cape)
-                    timed("dedupe_huge", st, [&] { hipLaunchKernelGGL(k_dedupe_heavy<false>, dim3(hb), dim3(256), 0, st, da, key_c, cape); });
+                // 64 < H <= 512: one wave per read; up to cape: a workgroup; beyond: global scratch
+                const unsigned mb = (unsigned)std::min<int64_t>(nr, 8192);
+                timed("dedupe_medium", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<true, 64>), dim3(mb), dim3(64), (size_t)512 * 8, st, da, key_c, 64u, 512u); });
+                if (maxH > 512) {
+                    const unsigned hb = (unsigned)std::min<int64_t>(nr, 2048);
+                    uint32_t N = 1;
+                    while (N < std::min(maxH, cape)) N <<= 1;
+                    timed("dedupe_heavy", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<true, 256>), dim3(hb), dim3(256), (size_t)N * 8, st, da, key_c, 512u, cape); });
+                    if (maxH > cape)
+                        timed("dedupe_huge", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<false, 256>), dim3(hb), dim3(256), 0, st, da, key_c, cape, 0xFFFFFFFFu); });
+                }
             }
             tb = scan_tmp_bytes(nr + 1);
             HIP_OK(scan_excl(scan_tmp, tb, CastU32{ccount, nr}, nr + 1, coff, st));
@@ -1528,7 +1704,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     nlong = zero_count;
                 }
                 WaveVerifyArgs wa{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
-                                  long_list, nlong, rule, RWL, TWL, Kp, dcap, vlim, steps, nullptr, 1, nullptr};
+                                  long_list, nlong, rule, RWL, TWL, Kw, dcap, vlim, steps, nullptr, 1, nullptr};
                 if (batched) {
                     // one persistent work-stealing launch for both tiles
                     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 4, 0u);
@@ -1561,34 +1737,71 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
                           pending_out, npending_out, nullptr, nullptr, req_loc, req_lim, req_list[0], nreq,
-                          pos, strand, dist, second, call};
+                          full_list[0], nfull, lane_lmax, pos, strand, dist, second, call};
             const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)nreq, 2, 0u);
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)nfull, 2, 0u);
             timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rb), dim3(256), 0, st, ra); });
-            if (final_pass && !all_lane) {
-                // verify what the replay asked for, replay those reads, until nothing is asked
+            if (final_pass) {
+                // verify what the replays ask for, replay those reads, until nothing is asked:
+                // whole short reads again with the full limit, single long-read locations
+                // with their exact limit
                 for (int it = 0;; it++) {
-                    unsigned long long nq = 0;
-                    HIP_OK(hipMemcpyAsync(&nq, nreq + (it & 1), 8, hipMemcpyDeviceToHost, st));
+                    const int cur = it & 1, nxt = (it + 1) & 1;
+                    unsigned long long cnts[2] = {0, 0};
+                    HIP_OK(hipMemcpyAsync(&cnts[0], nreq + cur, 8, hipMemcpyDeviceToHost, st));
+                    HIP_OK(hipMemcpyAsync(&cnts[1], nfull + cur, 8, hipMemcpyDeviceToHost, st));
                     HIP_OK(hipStreamSynchronize(st));
-                    if (nq == 0) break;
-                    WaveVerifyArgs wq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
-                                      req_loc, (const int64_t *)(nreq + (it & 1)), rule, RWL, TWL, Kp, dcap, vlim, steps,
-                                      batched ? steal_next : nullptr, 1, req_lim};
-                    if (batched) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 2, 0u);
-                    const unsigned wb = (unsigned)std::min<int64_t>((int64_t)nq, steal_waves);
-                    timed("verify_request", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wq); });
-                    ReplayArgs rq = ra;
-                    rq.rlist = req_list[it & 1];
-                    rq.rlist_n = nreq + (it & 1);
-                    rq.req_read = req_list[(it + 1) & 1];
-                    rq.nreq = nreq + ((it + 1) & 1);
-                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(nreq + ((it + 1) & 1)), 2, 0u);
-                    const unsigned rqb = (unsigned)std::min<int64_t>(((int64_t)nq + 3) / 4, 8192);
-                    timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rqb), dim3(256), 0, st, rq); });
+                    const unsigned long long nq = cnts[0], nf = cnts[1];
+                    if (nq == 0 && nf == 0) break;
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(nreq + nxt), 2, 0u);
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(nfull + nxt), 2, 0u);
+                    if (nf > 0) {
+                        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)route_cnt, 2, 0u);
+                        const unsigned eb = (unsigned)std::min<unsigned long long>((nf + 3) / 4, 8192);
+                        timed("expand", st, [&] { hipLaunchKernelGGL(k_expand_reads, dim3(eb), dim3(256), 0, st, full_list[cur], nfull + cur, coff, ccount, short_list, route_cnt); });
+                        Pass pf = ps;
+                        pf.Kcap = KCAP_NONE;
+                        const int kfull = std::min(Kmax, LANE_KMAX);
+                        const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
+                        const int kmf = kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63);
+                        const size_t ldsf = (size_t)64 * 4 * (2 * RW + 2 * TWf) + (size_t)64 * 2 * (2 * kmf + 3);
+                        VerifyArgs vf{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, pf, key_c, cread,
+                                      coff + nr, rule, RW, TWf, dcap, vlim, steps, short_list, (const int64_t *)route_cnt};
+                        const unsigned vb = (unsigned)((total + 63) / 64);
+                        timed("verify_full", st, [&] {
+                            if (kmf == 15)
+                                hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), ldsf, st, vf);
+                            else if (kmf == 31)
+                                hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), ldsf, st, vf);
+                            else
+                                hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), ldsf, st, vf);
+                        });
+                    }
+                    if (nq > 0) {
+                        WaveVerifyArgs wq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
+                                          req_loc, (const int64_t *)(nreq + cur), rule, RWL, TWL, Kw, dcap, vlim, steps,
+                                          batched ? steal_next : nullptr, 1, req_lim};
+                        if (batched) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 2, 0u);
+                        const unsigned wb = (unsigned)std::min<int64_t>((int64_t)nq, steal_waves);
+                        timed("verify_request", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wq); });
+                    }
+                    for (int which = 0; which < 2; which++) {
+                        const unsigned long long cnt = which ? nf : nq;
+                        if (cnt == 0) continue;
+                        ReplayArgs rq = ra;
+                        rq.rlist = which ? full_list[cur] : req_list[cur];
+                        rq.rlist_n = which ? nfull + cur : nreq + cur;
+                        rq.req_read = req_list[nxt];
+                        rq.nreq = nreq + nxt;
+                        rq.full_read = full_list[nxt];
+                        rq.nfull = nfull + nxt;
+                        const unsigned rqb = (unsigned)std::min<unsigned long long>((cnt + 3) / 4, 8192);
+                        timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rqb), dim3(256), 0, st, rq); });
+                    }
                     if (g_prof_on) {
                         std::lock_guard<std::mutex> g(g_prof_mu);
-                        g_ctr.requests += (int64_t)nq;
+                        g_ctr.requests += (int64_t)(nq + nf);
                     }
                 }
             }
@@ -1618,21 +1831,20 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         return SNAP_OK;
     };
 
-    // stage 1: the first pass1_seeds seeds, limit pass1_limit; stage 2: every
-    // seed, limit pass2_limit; stage 3: every seed, full limit. A stage runs on the
-    // reads the previous one could not settle; one that is complete settles all.
+    // stage 1 (when it is not complete): the first pass1_seeds seeds, limit
+    // pass1_limit; final stage: every seed. In the final stage, short reads'
+    // locations are verified first with limit final_limit and, for reads whose
+    // replay needs more, again with the full limit; long reads' locations are
+    // verified on request with the exact limit.
     struct Stage { int seeds, cap; };
-    Stage stages[3];
+    Stage stages[2];
     int nst = 0;
     {
         const int s1 = tune.pass1_seeds > 0 ? std::min(NS, tune.pass1_seeds) : NS;
         const int k1 = tune.pass1_limit > 0 && tune.pass1_limit < Kmax ? tune.pass1_limit : KCAP_NONE;
-        stages[nst++] = Stage{s1, k1};
-        if (!(s1 >= NS && k1 == KCAP_NONE)) {
-            const int k2 = tune.pass2_limit > 0 && tune.pass2_limit < Kmax ? tune.pass2_limit : KCAP_NONE;
-            if (k2 != KCAP_NONE && (s1 < NS || k2 > k1)) stages[nst++] = Stage{NS, k2};
-            stages[nst++] = Stage{NS, KCAP_NONE};
-        }
+        if (!(s1 >= NS && k1 == KCAP_NONE)) stages[nst++] = Stage{s1, k1};
+        const int kf = tune.final_limit > 0 && tune.final_limit < Kmax ? tune.final_limit : KCAP_NONE;
+        stages[nst++] = Stage{NS, kf};
     }
     unsigned long long *npend[2] = {npending, npending + 1};
     uint32_t *plist[2] = {pending, pending + n_reads};
