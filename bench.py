@@ -174,7 +174,9 @@ def bench_batched(args, w, dev):
     ml = int(reads.lengths.max())
     tuning = None
     tune_info = None
-    if not args.no_autotune:
+    if args.tuning:
+        tuning = tuple(int(x) for x in args.tuning.split(","))
+    elif not args.no_autotune:
         tune_info = autotune.tune(gix, rb, ln, d_max, params, batched=True, sample_reads=min(reads.n, 100_000),
                                   table_path=None, log=log)
         tuning = tuple(tune_info["tuning"])
@@ -354,6 +356,10 @@ def main():
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default="", help="fixed schedule a,b,c,d (snap_tuning fields); skips the autotuner")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run the library's plain copy kernel over this many bytes, 3 times "
+                         "(the known-size reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -371,6 +377,14 @@ def main():
         w = w.scaled(genome_len=args.genome_len or None, n_reads=args.reads or None)
     dev = torch.device("cuda:0")
     snapgpu.lib()
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            snapgpu.debug_copy(src, dst, args.copy_bytes)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_bytes} bytes 3 times, equal: {bool(torch.equal(src, dst))}")
+        return
     if args.workload == "batched":
         return bench_batched(args, w, dev)
     if args.workload == "served":
@@ -396,7 +410,10 @@ def main():
     wb = 4 * snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), max_len, w.params.d_max, params)
     ws = torch.empty(wb, dtype=torch.uint8, device=dev)
     tune_info = None
-    if not args.no_autotune:
+    if args.tuning:
+        snapgpu.set_tuning(*[int(x) for x in args.tuning.split(",")])
+        log(f"fixed schedule {snapgpu.get_tuning()}")
+    elif not args.no_autotune:
         from paper_1111_5572_amd import autotune
         tune_info = autotune.tune(gix, rb, ln, w.params.d_max, params, batched=False,
                                   sample_reads=min(reads.n, 1_000_000), table_path=None, log=log)

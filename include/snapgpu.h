@@ -151,15 +151,15 @@ int32_t snap_max_limit(void);
 /*
  * Output-invariant schedule of snap_align (process-wide). A first pass probes
  * only the first pass1_seeds seed slots of every read and verifies locations with
- * limit pass1_limit; Algorithm 1 is replayed on that, and a read is settled
- * whenever the replay never needs a seed or a distance beyond what the pass
- * computed. The reads left over go through a final pass with every seed: there,
- * short reads' locations are verified with limit final_limit first, and the reads
- * whose replay needs more are verified again with the full limit
- * d_max(L) + c - 1; long reads' locations are verified when the replay asks for
- * them, with exactly the limit it uses. 0 in a field means "no cap" (no first
- * pass when pass1_seeds and pass1_limit are both 0). Outputs never depend on
- * these values.
+ * limit pass1_limit; the final pass probes every seed slot of the reads left over
+ * and verifies with limit final_limit. In either pass Algorithm 1 is then replayed
+ * on what was computed; where a replay needs a distance above the limit a location
+ * was verified with, the read's undecided locations are verified again with the
+ * full limit d_max(L) + c - 1 (reads in the lane tile) or that location with
+ * exactly the limit the replay uses (longer reads), and the read is replayed
+ * again. Only reads that need more seeds than the first pass probed go on to the
+ * final pass. 0 in a field means "no cap" (no first pass when pass1_seeds and
+ * pass1_limit are both 0). Outputs never depend on these values.
  */
 typedef struct {
     int32_t pass1_seeds;
@@ -286,7 +286,7 @@ typedef struct {
     int64_t locations;    /* distinct (strand, p) locations verified */
     int64_t lv_steps;     /* diagonal extensions run by the verify kernel */
     int64_t second_pass_reads; /* reads a first pass left to a later pass */
-    int64_t requests;     /* long-read locations verified on request in the final pass */
+    int64_t requests;     /* replays of reads after the verification they asked for */
 } snap_counters;
 
 int snap_profile_counters(snap_counters *out);

@@ -48,11 +48,11 @@ class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "final_limit", "lane_max_len")]
 
     def astuple(self):
-        return (int(self.pass1_seeds), int(self.pass1_limit), int(self.final_limit), int(self.lane_max_len))
+        return tuple(int(getattr(self, n)) for n, _ in self._fields_)
 
 
 def set_tuning(pass1_seeds: int, pass1_limit: int, final_limit: int = 0, lane_max_len: int = 0):
-    """Output-invariant pass schedule and verify tile bound (see snap_set_tuning); 0 = no cap."""
+    """Output-invariant pass schedule and verify tiling (see snap_set_tuning); 0 = no cap."""
     _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, final_limit, lane_max_len))),
            "snap_set_tuning")
 

@@ -1,8 +1,8 @@
 """Autotuner for the output-invariant knobs of snap_align / snap_align_batched.
 
 The knobs (snap_tuning): the seeds and verify limit of the first pass, the first
-verify limit of the final pass, and the verify tile bound (reads up to that
-length get one lane per location, longer ones a wave per location). Outputs do
+verify limit of the final pass, the verify tile bound (reads up to that length
+get one lane per location, longer ones a wave per location). Outputs do
 not depend on them; only the time does. The tuner aligns a sample of the batch
 with each candidate, keeps the fastest, and records it in a JSON table keyed by
 the batch's read-length class.
@@ -22,19 +22,18 @@ TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_ta
 # (pass1_seeds, pass1_limit, final_limit, lane_max_len); 0 = no cap / default
 CANDIDATES = [
     (0, 0, 0, 0),
-    (0, 0, 2, 0),
-    (0, 0, 3, 0),
-    (0, 0, 4, 0),
-    (0, 0, 6, 0),
-    (4, 0, 3, 0),
-    (4, 0, 4, 0),
-    (6, 0, 3, 0),
-    (6, 0, 4, 0),
+    (0, 3, 3, 0),
     (6, 0, 0, 0),
+    (6, 2, 2, 0),
+    (6, 3, 3, 0),
+    (6, 4, 4, 0),
+    (6, 5, 5, 0),
+    (4, 3, 3, 0),
     (4, 4, 4, 0),
-    (6, 0, 4, 256),
-    (6, 0, 4, 128),
-    (8, 0, 8, 0),
+    (8, 3, 3, 0),
+    (8, 4, 4, 0),
+    (6, 4, 4, 256),
+    (6, 4, 4, 128),
 ]
 
 

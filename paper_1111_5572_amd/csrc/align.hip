@@ -49,6 +49,18 @@ constexpr int VERIFY_KMAX = 1023;   // largest limit d_max(L) + c - 1
 constexpr int VERIFY_LMAX = 16384;  // longest read
 constexpr int LANE_KMAX = 63;       // lane-per-location verify: limit and read length bounds
 constexpr int LANE_LMAX = 512;
+// Verification requests live in one int16 per location: the limit, tagged for the
+// wave tile when the read is verified a wave per location; -1 = none.
+constexpr int REQ_WAVE = 0x4000;
+constexpr int REQ_LIMIT_MASK = 0x3FFF;
+// A short read's replay asks for single locations at exactly the limit it uses for
+// this many rounds; after that for every undecided location at the full limit.
+constexpr int REQ_EXACT_ROUNDS = 3;
+constexpr uint32_t REQ_WAVE_READ = 0x80000000u;
+// Outcome of a read's replay in a pass.
+constexpr uint8_t RF_DONE = 0;      // outputs written
+constexpr uint8_t RF_PENDING = 1;   // needs a seed this pass did not probe
+constexpr uint8_t RF_REPLAY = 2;    // asked for verification; replay again
 
 struct ProbeRec {
     uint64_t off_f;   // first forward hit (positions index)
@@ -583,6 +595,7 @@ struct VerifyArgs {
     uint32_t *steps;            // per-location diagonal extensions (profiling only, else null)
     const uint32_t *list;       // locations routed to this kernel (null: all)
     const int64_t *nlist_ptr;   // their number when list is set
+    int16_t *rq;                // requested limit per location (null: the read's limit); cleared once verified
 };
 
 // Per-lane LDS arrays are laid out [word][lane], so a wave's accesses to its
@@ -678,7 +691,7 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
     const int strand = (int)(key & 1);
     const int64_t g = gid(a.ps, a.cread[k]);
     const int L = a.len[g];
-    const int K = min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
+    const int K = a.rq ? (int)a.rq[k] : min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
     const int64_t xb = STREAM_GUARD + a.roff[g];
     const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
 
@@ -714,7 +727,7 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
     const int D = anyn ? lv_lane<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane<KMAX, false>(st, L, Tn, K, nsteps);
     a.dcap[k] = (uint16_t)D;
     a.vlim[k] = (int16_t)K;
-    if (a.steps) a.steps[k] = nsteps;
+    if (a.steps) a.steps[k] = (a.rq ? a.steps[k] : 0u) + nsteps;
 }
 
 
@@ -722,9 +735,9 @@ template <int KMAX>
 __global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
     extern __shared__ uint32_t sm[];
     const int lane = threadIdx.x;
-    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
-    if (idx >= (a.list ? *a.nlist_ptr : *a.ncand_ptr)) return;
-    verify_lane<KMAX>(a, a.list ? (int64_t)a.list[idx] : idx, sm);
+    const int64_t n = a.list ? *a.nlist_ptr : *a.ncand_ptr;
+    for (int64_t idx = (int64_t)blockIdx.x * 64 + lane; idx < n; idx += (int64_t)gridDim.x * 64)
+        verify_lane<KMAX>(a, a.list ? (int64_t)a.list[idx] : idx, sm);
 }
 
 // Locations whose read or limit is too large for one lane: one wave per location.
@@ -749,7 +762,8 @@ struct WaveVerifyArgs {
     uint32_t *steps;
     unsigned long long *next;   // shared work counter (work-stealing launches), null: static stride
     int32_t grab;               // locations taken per grab
-    const int32_t *req_lim;     // per list entry: the limit to verify with (null: the read's full limit)
+    int16_t *rq;                // requested limit per location, tagged REQ_WAVE (null: the read's limit);
+                                // cleared once verified
 };
 
 __device__ inline uint32_t lds_w16(const uint32_t *A, int i) {
@@ -771,8 +785,7 @@ __device__ inline int wave_slide(const uint32_t *RC, const uint32_t *RN, const u
     }
 }
 
-__device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t idx, uint32_t *sm) {
-    const int64_t k = a.list ? (int64_t)a.list[idx] : idx;
+__device__ inline void verify_loc_wave(const WaveVerifyArgs &a, int64_t k, uint32_t *sm) {
     const int lane = threadIdx.x;
     uint32_t *RC = sm, *RN = RC + a.RW, *TC = RN + a.RW, *TN = TC + a.TW;
     int *F0 = reinterpret_cast<int *>(TN + a.TW), *F1 = F0 + (2 * a.KL + 3);
@@ -781,7 +794,7 @@ __device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t idx, uin
     const int strand = (int)(key & 1);
     const int64_t g = gid(a.ps, a.cread[k]);
     const int L = a.len[g];
-    const int K = a.req_lim ? a.req_lim[idx] : min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
+    const int K = a.rq ? ((int)a.rq[k] & REQ_LIMIT_MASK) : min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
     const int64_t xb = STREAM_GUARD + a.roff[g];
     const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + max(K, 0));
     const int nrw = (L + 15) >> 4, ntw = (Tn + 15) >> 4;
@@ -844,9 +857,13 @@ __device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t idx, uin
     if (lane == 0) {
         a.dcap[k] = (uint16_t)D;
         a.vlim[k] = (int16_t)K;
-        if (a.steps) a.steps[k] = (a.req_lim ? a.steps[k] : 0u) + nsteps;
+        if (a.steps) a.steps[k] = (a.rq ? a.steps[k] : 0u) + nsteps;
     }
     __syncthreads();
+}
+
+__device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t idx, uint32_t *sm) {
+    verify_loc_wave(a, a.list ? (int64_t)a.list[idx] : idx, sm);
 }
 
 __global__ __launch_bounds__(64) void k_verify_wave(WaveVerifyArgs a) {
@@ -866,6 +883,63 @@ __global__ __launch_bounds__(64) void k_verify_wave(WaveVerifyArgs a) {
     }
 }
 
+
+// Verification requests of the reads being replayed.
+struct RequestArgs {
+    const uint32_t *rlist;      // chunk reads being replayed
+    const int64_t *n_ptr;       // how many
+    const uint32_t *reqcount;   // per read: locations asked for (REQ_WAVE_READ: wave tile)
+    const uint32_t *req_area;   // the locations, listed at the read's first location slot
+    const int64_t *coff;        // first location slot of each read
+};
+
+// Requested locations per replayed read for the lane tile (0 for wave-tile reads).
+struct LaneReqCount {
+    const uint32_t *rlist, *reqcount;
+    int64_t n;
+    __host__ __device__ int64_t operator()(int64_t i) const {
+        if (i >= n) return 0;
+        const uint32_t c = reqcount[rlist[i]];
+        return (c & REQ_WAVE_READ) ? 0 : (int64_t)c;
+    }
+};
+
+// Lane tile: the requested locations of all replayed reads, one list (a wave per
+// read copies its own at its offset; the last offset is the total).
+__global__ __launch_bounds__(256) void k_flatten_requests(RequestArgs q, const int64_t *offs, uint32_t *out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n = *q.n_ptr;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+        const uint32_t r = q.rlist[i];
+        const uint32_t c = q.reqcount[r];
+        if (c & REQ_WAVE_READ) continue;
+        const int64_t base = q.coff[r], dst = offs[i];
+        for (uint32_t k = lane; k < c; k += 64) out[dst + k] = q.req_area[base + k];
+    }
+}
+
+// Wave tile: one wave per read of the replay list, its requested locations one at a
+// time (work stealing over reads when `next` is set).
+__global__ __launch_bounds__(64) void k_verify_requests_wave(WaveVerifyArgs a, RequestArgs q) {
+    extern __shared__ uint32_t wsm[];
+    const int64_t n = *q.n_ptr;
+    for (int64_t idx = blockIdx.x;;) {
+        if (a.next) {
+            unsigned long long f = 0;
+            if (threadIdx.x == 0) f = atomicAdd(a.next, 1ull);
+            idx = (int64_t)__shfl((unsigned long long)f, 0, 64);
+        }
+        if (idx >= n) break;
+        const uint32_t r = q.rlist[idx];
+        const uint32_t c = q.reqcount[r];
+        if (c & REQ_WAVE_READ) {
+            const int64_t base = q.coff[r];
+            for (uint32_t i = 0; i < (c & ~REQ_WAVE_READ); i++) verify_loc_wave(a, (int64_t)q.req_area[base + i], wsm);
+        }
+        if (!a.next) idx += gridDim.x;
+    }
+}
 
 // Batched form: one persistent launch verifies every location of a pass. Each wave
 // first takes long locations one at a time (wave tile), then groups of 64 short
@@ -908,24 +982,6 @@ __global__ __launch_bounds__(64) void k_verify_steal(StealArgs a) {
             const int64_t idx = gi * 64 + lane;
             if (idx < nshort) verify_lane<KMAX>(a.va, (int64_t)a.va.list[idx], ssm);
         }
-    }
-}
-
-// Every location of the listed reads, appended to a verify list (one wave per read).
-__global__ __launch_bounds__(256) void k_expand_reads(const uint32_t *reads, const unsigned long long *n_ptr,
-                                                      const int64_t *coff, const uint32_t *count, uint32_t *out,
-                                                      unsigned long long *nout) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t n = (int64_t)*n_ptr;
-    for (int64_t q = wave; q < n; q += nwaves) {
-        const uint32_t r = reads[q];
-        const int64_t base = coff[r], C = count[r];
-        unsigned long long at = 0;
-        if (lane == 0) at = atomicAdd(nout, (unsigned long long)C);
-        at = __shfl(at, 0, 64);
-        for (int64_t k = lane; k < C; k += 64) out[at + k] = (uint32_t)(base + k);
     }
 }
 
@@ -999,16 +1055,13 @@ struct ReplayArgs {
     Pass ps;
     Rule rule;
     Shifts sh;
-    uint32_t *pending;          // reads this pass could not settle (non-final passes)
-    unsigned long long *npending;
+    uint8_t *rflag;             // per chunk read: RF_DONE / RF_PENDING / RF_REPLAY
+    int16_t *rq;                // per location: requested verify limit (REQ_WAVE-tagged for long reads)
+    uint32_t *req_area;         // per read, at its first location slot: the locations it asks for
+    uint32_t *reqcount;         // per chunk read: how many (REQ_WAVE_READ set for the wave tile)
     const uint32_t *rlist;      // chunk reads to replay (null: all nr)
-    const unsigned long long *rlist_n;
-    uint32_t *req_loc;          // final pass: the location each unsettled read needs verified,
-    int32_t *req_lim;           //   the limit to verify it with,
-    uint32_t *req_read;         //   and the read (replayed again once it is verified)
-    unsigned long long *nreq;
-    uint32_t *full_read;        // final pass, short reads: reads whose locations are re-verified at K
-    unsigned long long *nfull;
+    const int64_t *rlist_n;
+    int32_t round;              // 0 for the first replay of the chunk, then 1, 2, ...
     int32_t lane_lmax;          // reads up to this length (limit <= 63) are verified one lane per location
     int64_t *pos;
     int8_t *strand;
@@ -1051,6 +1104,37 @@ __device__ inline void state_update(ReadState &st, int64_t rep, int vd, int64_t 
     } else if (vd < st.d_second) {
         st.d_second = vd;
     }
+}
+
+// A read's verification requests: the locations whose `want` is set (all lanes of
+// the wave call this together), each with limit `code`, listed at the read's first
+// location slot.
+__device__ inline void light_request(const ReplayArgs &a, int64_t base, int64_t r, bool want, int code,
+                                     bool wave_tile, int lane) {
+    const uint64_t b = __ballot(want);
+    if (want) {
+        a.rq[base + lane] = (int16_t)code;
+        a.req_area[base + __popcll(b & ((1ull << lane) - 1))] = (uint32_t)(base + lane);
+    }
+    if (lane == 0) a.reqcount[r] = (uint32_t)__popcll(b) | (wave_tile ? REQ_WAVE_READ : 0u);
+}
+
+// Same for reads whose locations are in global memory: `want(k)` over all of them.
+template <class Want>
+__device__ inline void heavy_request(const ReplayArgs &a, int64_t base, int64_t C, int64_t r, Want want, int code,
+                                     bool wave_tile, int lane) {
+    uint32_t n = 0;
+    for (int64_t k0 = 0; k0 < C; k0 += 64) {
+        const int64_t k = k0 + lane;
+        const bool w = k < C && want(k);
+        const uint64_t b = __ballot(w);
+        if (w) {
+            a.rq[base + k] = (int16_t)code;
+            a.req_area[base + n + __popcll(b & ((1ull << lane) - 1))] = (uint32_t)(base + k);
+        }
+        n += (uint32_t)__popcll(b);
+    }
+    if (lane == 0) a.reqcount[r] = n | (wave_tile ? REQ_WAVE_READ : 0u);
 }
 
 // Reads with at most 64 locations: location k lives in lane k's registers (key,
@@ -1122,17 +1206,22 @@ __device__ inline int ed_answer(int dc, int vl, int lim) {
 // Algorithm 1's control flow over the seed masks and capped distances of one read,
 // one wave per read. A call is answered from the location's capped distance; when
 // that does not decide it (the location was verified with a limit below the one
-// Algorithm 1 asks for), a non-final pass leaves the read to the next pass and
-// the final pass requests verification of exactly that location with exactly that
-// limit, then replays the read once the answer exists. The phase that scores every
-// remaining location only changes state at calls that return a distance, so it
-// scans for the next such location in selection order (vote count descending,
-// then p, then strand) instead of visiting each one.
+// Algorithm 1 asks for), the read records a verification request and is replayed
+// once it is answered. A short read (lane tile) asks for that location at exactly
+// that limit in its first rounds, for every location it has not decided at the
+// full limit after that, and, in the phase that scores every remaining location,
+// for every remaining undecided location at the current limit (the limit only
+// shrinks as results come in, up to rare steps of one); a long read always asks for
+// the single location at the exact limit. A read that needs a seed this pass did
+// not probe is left to the next pass. The phase that scores every remaining
+// location only changes state at calls that return a distance, so it scans for the
+// next such location in selection order (vote count descending, then p, then
+// strand) instead of visiting each one.
 __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t nlist = a.rlist ? (int64_t)*a.rlist_n : a.ps.nr;
+    const int64_t nlist = a.rlist ? *a.rlist_n : a.ps.nr;
     for (int64_t ri = wave; ri < nlist; ri += nwaves) {
         const int64_t r = a.rlist ? (int64_t)a.rlist[ri] : ri;
         const int64_t g = gid(a.ps, r);
@@ -1141,12 +1230,14 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         const int NS = a.ps.NS;
         const int64_t base = a.coff[r];
         const int64_t C = a.count[r];
+        const int Kfull = dmax + c - 1;
+        const bool lane_class = L <= a.lane_lmax && Kfull <= LANE_KMAX;
+        const bool all_undecided = lane_class && a.round >= REQ_EXACT_ROUNDS;
         ReadState st{DINF, DINF, -1, -1, -1};
         const int round0 = L / a.rule.s;
         int t = 0, call = -1;
         bool looked = false, all_over = true, ended = false, unresolved = false;
         int64_t need_k = -1;
-        int need_lim = 0;
         uint32_t prefix = 0;
         if (C <= 64) {
             // ---- registers: location `lane`
@@ -1189,7 +1280,15 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                     const int kb = (int)(0xFFFFFFFFu - (uint32_t)(v & 0xFFFFFFFFull));
                     const int lim = d_limit(st, dmax, c);
                     const int res = ed_answer(__shfl(dc, kb, 64), __shfl(vl, kb, 64), lim);
-                    if (res == -2) { unresolved = true; need_k = kb; need_lim = lim; break; }
+                    if (res == -2) {
+                        unresolved = true;
+                        need_k = kb;
+                        if (all_undecided)
+                            light_request(a, base, r, have && dc > vl && vl < Kfull, Kfull, false, lane);
+                        else
+                            light_request(a, base, r, lane == kb, lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
+                        break;
+                    }
                     if (lane == kb) scored = true;
                     if (res >= 0) light_record(kb, res, st, key, rep, bmin, lane);
                 }
@@ -1210,7 +1309,13 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                             if ((__ballot(res == -2) >> j) & 1) {
                                 unresolved = true;
                                 need_k = j;
-                                need_lim = lim;
+                                if (lane_class) {
+                                    const int lr = all_undecided ? Kfull : lim;
+                                    light_request(a, base, r, have && !scored && (mask & prefix) && dc > vl && vl < lr,
+                                                  lr, false, lane);
+                                } else {
+                                    light_request(a, base, r, lane == j, REQ_WAVE | lim, true, lane);
+                                }
                                 break;
                             }
                             light_record(j, __shfl(res, j, 64), st, key, rep, bmin, lane);
@@ -1249,7 +1354,20 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                 const int64_t kb = (int64_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
                 const int lim = d_limit(st, dmax, c);
                 const int res = ed_answer(a.dcap[base + kb], a.vlim[base + kb], lim);
-                if (res == -2) { unresolved = true; need_k = kb; need_lim = lim; break; }
+                if (res == -2) {
+                    unresolved = true;
+                    need_k = kb;
+                    if (all_undecided) {
+                        heavy_request(a, base, C, r, [&](int64_t k) {
+                            const int dck = a.dcap[base + k], vlk = a.vlim[base + k];
+                            return dck > vlk && vlk < Kfull;
+                        }, Kfull, false, lane);
+                    } else {
+                        heavy_request(a, base, C, r, [&](int64_t k) { return k == kb; },
+                                      lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
+                    }
+                    break;
+                }
                 if (lane == 0) a.scored[base + kb] = 1;
                 if (res >= 0) wave_record(a, base, kb, res, st, lane);
             }
@@ -1280,7 +1398,16 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                             if ((__ballot(un) >> j) & 1) {
                                 unresolved = true;
                                 need_k = c0 + j;
-                                need_lim = lim;
+                                if (lane_class) {
+                                    const int lr = all_undecided ? Kfull : lim;
+                                    heavy_request(a, base, C, r, [&](int64_t k2) {
+                                        const int dck = a.dcap[base + k2], vlk = a.vlim[base + k2];
+                                        return !a.scored[base + k2] && (a.mask[base + k2] & prefix) && dck > vlk && vlk < lr;
+                                    }, lr, false, lane);
+                                } else {
+                                    const int64_t kq = c0 + j;
+                                    heavy_request(a, base, C, r, [&](int64_t k2) { return k2 == kq; }, REQ_WAVE | lim, true, lane);
+                                }
                                 break;
                             }
                             const int dj = __shfl(res, j, 64);
@@ -1299,21 +1426,8 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         if (!ended && !unresolved && NS < seeds_for_length(a.rule, L) && seed_offset(a.sh, a.rule.s, L, NS) >= 0)
             unresolved = true;
         if (unresolved) {
-            if (lane == 0) {
-                const bool lane_class = L <= a.lane_lmax && dmax + c - 1 <= LANE_KMAX;
-                if (!a.ps.final_pass || need_k < 0) {
-                    a.pending[atomicAdd(a.npending, 1ull)] = (uint32_t)g;
-                } else if (lane_class) {
-                    // every location of the read again, with the full limit
-                    a.full_read[atomicAdd(a.nfull, 1ull)] = (uint32_t)r;
-                } else {
-                    // that location, with exactly the limit Algorithm 1 uses there
-                    const unsigned long long q = atomicAdd(a.nreq, 1ull);
-                    a.req_loc[q] = (uint32_t)(base + need_k);
-                    a.req_lim[q] = need_lim;
-                    a.req_read[q] = (uint32_t)r;
-                }
-            }
+            // a distance is missing (requests recorded above) or a seed is
+            if (lane == 0) a.rflag[r] = need_k < 0 ? RF_PENDING : RF_REPLAY;
             continue;
         }
         if (call < 0) {
@@ -1323,6 +1437,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         }
         if (lane == 0) {
             const bool has = st.d_best < DINF;
+            a.rflag[r] = RF_DONE;
             a.pos[g] = has ? st.best_p : -1;
             a.strand[g] = (int8_t)(has ? st.best_s : -1);
             a.dist[g] = has ? st.d_best : -1;
@@ -1330,6 +1445,13 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             a.call[g] = (int8_t)call;
         }
     }
+}
+
+// Chunk read indices -> global read ids (the list a later pass works on).
+__global__ void k_map_gid(const uint32_t *in, const int64_t *n_ptr, Pass ps, uint32_t *out) {
+    const int64_t n = *n_ptr;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (uint32_t)gid(ps, in[i]);
 }
 
 // For each read in the chunk, the largest prefix [0, k) whose reserved region fits.
@@ -1359,13 +1481,33 @@ hipError_t scan_excl(void *tmp, size_t &tmp_bytes, F f, int64_t items, int64_t *
     return hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, it, out, (int)items, st);
 }
 
+// Stream compaction of indices [0, items) by a predicate on the index.
+struct FlagPred {
+    const uint8_t *f;
+    uint8_t v;
+    __host__ __device__ bool operator()(uint32_t r) const { return f[r] == v; }
+};
+
+template <class P>
+hipError_t select_idx(void *tmp, size_t &tmp_bytes, int64_t items, P pred, uint32_t *out, int64_t *nsel,
+                      hipStream_t st) {
+    hipcub::CountingInputIterator<uint32_t> ci(0);
+    return hipcub::DeviceSelect::If(tmp, tmp_bytes, ci, out, nsel, (int)items, pred, st);
+}
+
+size_t select_tmp_bytes(int64_t items) {
+    size_t b = 0;
+    (void)select_idx(nullptr, b, items, FlagPred{nullptr, 0}, nullptr, nullptr, 0);
+    return b;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     // batch part
     size_t off_roff, off_rcode, off_rmask, off_misc, off_pending;
     // chunk part
-    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan, off_req, off_pool;
+    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan, off_sel, off_req, off_pool;
     int64_t R;             // reads per chunk
     int64_t pool_slots;    // hit / location slots per chunk
     size_t total;
@@ -1373,9 +1515,9 @@ struct Layout {
 
 // pool arrays per slot: hit 8, location key 8 + mask 4 + slot read 4 (by read),
 // compacted key 8 + mask 4 + read 4, bucket minimum 8, capped distance 2, verified
-// limit 2, scored flag 1, verify routing lists 4 + 4
-constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 2 + 2 + 1 + 4 + 4;
-constexpr int POOL_ARRAYS = 13;
+// limit 2, scored flag 1, verify routing lists / requests 4 + 4, requested limit 2
+constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 2 + 2 + 1 + 4 + 4 + 2;
+constexpr int POOL_ARRAYS = 14;
 
 size_t scan_tmp_bytes(int64_t items) {
     size_t b = 0;
@@ -1400,10 +1542,13 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     l.off_ccount = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
     l.off_coff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
     l.off_scan = o; o = align256(o + std::max(scan_tmp_bytes(R + 1), scan_tmp_bytes(n + 1)));
-    l.off_req = o; o = align256(o + 6 * sizeof(uint32_t) * (size_t)R);   // location, limit, four read lists
+    // read flags; replay and next-pass lists, request counts; request offsets
+    l.off_req = o; o = align256(o + (size_t)R); o = align256(o + 3 * sizeof(uint32_t) * (size_t)R);
+    o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
     const int64_t minslots = (int64_t)NS * hmax;
     if (pool_slots < minslots) pool_slots = minslots;
     l.pool_slots = pool_slots;
+    l.off_sel = o; o = align256(o + select_tmp_bytes(R + 1));
     l.off_pool = o; o = align256(o + POOL_SLOT_BYTES * (size_t)pool_slots + POOL_ARRAYS * 256);
     l.total = o;
     return l;
@@ -1449,7 +1594,7 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {6, 0, 4, 0};   // stage-1 seeds and limit, final first limit, lane-tile read bound
+snap_tuning g_tune = {6, 4, 4, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound
 
 constexpr int KCAP_NONE = 1 << 20;
 
@@ -1553,15 +1698,18 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     {
         int64_t extra = (int64_t)((ws_bytes - l.total) / POOL_SLOT_BYTES);
         l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots + extra);
-        while (l.total > ws_bytes) l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots - 64);
+        while (l.total > ws_bytes) {
+            const int64_t over = (int64_t)((l.total - ws_bytes) / POOL_SLOT_BYTES) + 64;
+            l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots - over);
+        }
     }
     uint32_t *rcode = (uint32_t *)(ws + l.off_rcode);
     uint32_t *rmask = (uint32_t *)(ws + l.off_rmask);
     int64_t *misc = (int64_t *)(ws + l.off_misc);
-    unsigned long long *npending = (unsigned long long *)(misc + 4);   // two counters
     unsigned long long *steps_sum = (unsigned long long *)(misc + 6);
+    int64_t *sel_n = misc + 20;   // selected counts: [2] reads to replay, [3] reads for the next pass
     uint32_t *pending_out = nullptr;
-    unsigned long long *npending_out = nullptr;
+    int64_t pend_count = 0;
     uint32_t *pending = (uint32_t *)(ws + l.off_pending);
     ProbeRec *probe = (ProbeRec *)(ws + l.off_probe);
     uint32_t *hits = (uint32_t *)(ws + l.off_hits);
@@ -1569,10 +1717,13 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     uint32_t *ccount = (uint32_t *)(ws + l.off_ccount);
     int64_t *coff = (int64_t *)(ws + l.off_coff);
     void *scan_tmp = ws + l.off_scan;
-    uint32_t *req_loc = (uint32_t *)(ws + l.off_req);
-    int32_t *req_lim = (int32_t *)(req_loc + R);
-    uint32_t *req_list[2] = {(uint32_t *)(req_lim + R), (uint32_t *)(req_lim + R) + R};
-    uint32_t *full_list[2] = {req_list[1] + R, req_list[1] + 2 * R};
+    void *sel_tmp = ws + l.off_sel;
+    size_t sel_tb = select_tmp_bytes(R + 1);
+    uint8_t *rflag = (uint8_t *)(ws + l.off_req);
+    uint32_t *replay_list = (uint32_t *)(ws + align256(l.off_req + (size_t)R));
+    uint32_t *pend_local = replay_list + R;
+    uint32_t *reqcount = pend_local + R;
+    int64_t *req_off = (int64_t *)(ws + align256(l.off_req + (size_t)R) + align256(3 * sizeof(uint32_t) * (size_t)R));
     const int64_t PS = l.pool_slots;
     char *pool = ws + l.off_pool;
     auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
@@ -1589,16 +1740,16 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     uint8_t *scored = (uint8_t *)carve((size_t)PS);
     uint32_t *short_list = (uint32_t *)carve(4 * (size_t)PS);
     uint32_t *long_list = (uint32_t *)carve(4 * (size_t)PS);
+    int16_t *rq = (int16_t *)carve(2 * (size_t)PS);
     unsigned long long *route_cnt = (unsigned long long *)(misc + 8);   // two counters
     unsigned long long *steal_next = (unsigned long long *)(misc + 10);  // two cursors
-    unsigned long long *nreq = (unsigned long long *)(misc + 12);        // two request counters
     const int64_t *zero_count = (const int64_t *)(misc + 14);
-    unsigned long long *nfull = (unsigned long long *)(misc + 16);       // two full-read counters
     int64_t steal_waves = 2048;
+    int cus = 256;
     {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            steal_waves = (int64_t)cus * 8;
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0) cus = c;
+        steal_waves = (int64_t)cus * 8;
     }
     if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
     // per-location step counts reuse the hit array, dead once locations are compacted
@@ -1619,9 +1770,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int TW = (std::max(lane_L, 1) + lane_K + 15) / 16 + 1;
         const int kmax_t = lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63);
         const size_t lds = (size_t)64 * 4 * (2 * RW + 2 * TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
-        // wave-per-location tile: any read, any limit (the final pass verifies on
-        // request up to the full limit)
-        const int Kw = final_pass ? Kmax : Kp;
+        // wave-per-location tile: any read, any limit (requests go up to the full limit)
+        const int Kw = Kmax;
         const int RWL = (std::max(maxL, 1) + 15) / 16 + 1;
         const int TWL = (std::max(maxL, 1) + Kw + 15) / 16 + 1;
         const size_t lds_wave = (size_t)4 * (2 * RWL + 2 * TWL) + (size_t)8 * (2 * Kw + 3);
@@ -1736,74 +1886,69 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
-                          pending_out, npending_out, nullptr, nullptr, req_loc, req_lim, req_list[0], nreq,
-                          full_list[0], nfull, lane_lmax, pos, strand, dist, second, call};
+                          rflag, rq, short_list, reqcount, nullptr, nullptr, 0, lane_lmax, pos, strand, dist, second, call};
             const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)nreq, 2, 0u);
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)nfull, 2, 0u);
             timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rb), dim3(256), 0, st, ra); });
-            if (final_pass) {
-                // verify what the replays ask for, replay those reads, until nothing is asked:
-                // whole short reads again with the full limit, single long-read locations
-                // with their exact limit
-                for (int it = 0;; it++) {
-                    const int cur = it & 1, nxt = (it + 1) & 1;
-                    unsigned long long cnts[2] = {0, 0};
-                    HIP_OK(hipMemcpyAsync(&cnts[0], nreq + cur, 8, hipMemcpyDeviceToHost, st));
-                    HIP_OK(hipMemcpyAsync(&cnts[1], nfull + cur, 8, hipMemcpyDeviceToHost, st));
-                    HIP_OK(hipStreamSynchronize(st));
-                    const unsigned long long nq = cnts[0], nf = cnts[1];
-                    if (nq == 0 && nf == 0) break;
-                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(nreq + nxt), 2, 0u);
-                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(nfull + nxt), 2, 0u);
-                    if (nf > 0) {
-                        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)route_cnt, 2, 0u);
-                        const unsigned eb = (unsigned)std::min<unsigned long long>((nf + 3) / 4, 8192);
-                        timed("expand", st, [&] { hipLaunchKernelGGL(k_expand_reads, dim3(eb), dim3(256), 0, st, full_list[cur], nfull + cur, coff, ccount, short_list, route_cnt); });
-                        Pass pf = ps;
-                        pf.Kcap = KCAP_NONE;
-                        const int kfull = std::min(Kmax, LANE_KMAX);
-                        const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
-                        const int kmf = kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63);
-                        const size_t ldsf = (size_t)64 * 4 * (2 * RW + 2 * TWf) + (size_t)64 * 2 * (2 * kmf + 3);
-                        VerifyArgs vf{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, pf, key_c, cread,
-                                      coff + nr, rule, RW, TWf, dcap, vlim, steps, short_list, (const int64_t *)route_cnt};
-                        const unsigned vb = (unsigned)((total + 63) / 64);
-                        timed("verify_full", st, [&] {
-                            if (kmf == 15)
-                                hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), ldsf, st, vf);
-                            else if (kmf == 31)
-                                hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), ldsf, st, vf);
-                            else
-                                hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), ldsf, st, vf);
-                        });
-                    }
-                    if (nq > 0) {
-                        WaveVerifyArgs wq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
-                                          req_loc, (const int64_t *)(nreq + cur), rule, RWL, TWL, Kw, dcap, vlim, steps,
-                                          batched ? steal_next : nullptr, 1, req_lim};
-                        if (batched) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 2, 0u);
-                        const unsigned wb = (unsigned)std::min<int64_t>((int64_t)nq, steal_waves);
-                        timed("verify_request", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wq); });
-                    }
-                    for (int which = 0; which < 2; which++) {
-                        const unsigned long long cnt = which ? nf : nq;
-                        if (cnt == 0) continue;
-                        ReplayArgs rq = ra;
-                        rq.rlist = which ? full_list[cur] : req_list[cur];
-                        rq.rlist_n = which ? nfull + cur : nreq + cur;
-                        rq.req_read = req_list[nxt];
-                        rq.nreq = nreq + nxt;
-                        rq.full_read = full_list[nxt];
-                        rq.nfull = nfull + nxt;
-                        const unsigned rqb = (unsigned)std::min<unsigned long long>((cnt + 3) / 4, 8192);
-                        timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rqb), dim3(256), 0, st, rq); });
-                    }
-                    if (g_prof_on) {
-                        std::lock_guard<std::mutex> g(g_prof_mu);
-                        g_ctr.requests += (int64_t)(nq + nf);
-                    }
+            // verify what the replays asked for, replay those reads, until nothing is asked
+            for (int round = 1;; round++) {
+                int64_t nrep = 0;
+                HIP_OK(select_idx(sel_tmp, sel_tb, nr, FlagPred{rflag, RF_REPLAY}, replay_list, sel_n + 2, st));
+                HIP_OK(hipMemcpyAsync(&nrep, sel_n + 2, 8, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
+                if (nrep == 0) break;
+                RequestArgs qa{replay_list, sel_n + 2, reqcount, short_list, coff};
+                {
+                    // lane tile: one list of every requested location, each verified at the
+                    // limit its read asked for
+                    size_t tb = scan_tmp_bytes(nrep + 1);
+                    HIP_OK(scan_excl(scan_tmp, tb, LaneReqCount{replay_list, reqcount, nrep}, nrep + 1, req_off, st));
+                    const unsigned fb = (unsigned)std::min<int64_t>((nrep + 3) / 4, 8192);
+                    hipLaunchKernelGGL(k_flatten_requests, dim3(fb), dim3(256), 0, st, qa, req_off, long_list);
+                    const int kfull = std::min(Kmax, LANE_KMAX);
+                    const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
+                    const int kmf = kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63);
+                    const size_t ldsf = (size_t)64 * 4 * (2 * RW + 2 * TWf) + (size_t)64 * 2 * (2 * kmf + 3);
+                    VerifyArgs vq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
+                                  coff + nr, rule, RW, TWf, dcap, vlim, steps, long_list, req_off + nrep, rq};
+                    // as many waves as fit the device (the count is on the device)
+                    const unsigned vb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)cus * 16));
+                    timed("verify_request", st, [&] {
+                        if (kmf == 15)
+                            hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), ldsf, st, vq);
+                        else if (kmf == 31)
+                            hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), ldsf, st, vq);
+                        else
+                            hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), ldsf, st, vq);
+                    });
                 }
+                if (!all_lane) {
+                    // wave tile, each location at exactly the limit its read uses there
+                    WaveVerifyArgs wq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
+                                      nullptr, nullptr, rule, RWL, TWL, Kw, dcap, vlim, steps,
+                                      batched ? steal_next : nullptr, 1, rq};
+                    if (batched) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 2, 0u);
+                    const unsigned wb = (unsigned)std::min<int64_t>(nrep, steal_waves);
+                    timed("verify_request_wave", st, [&] { hipLaunchKernelGGL(k_verify_requests_wave, dim3(wb), dim3(64), lds_wave, st, wq, qa); });
+                }
+                ReplayArgs rr = ra;
+                rr.rlist = replay_list;
+                rr.rlist_n = sel_n + 2;
+                rr.round = round;
+                const unsigned rqb = (unsigned)std::min<int64_t>((nrep + 3) / 4, 8192);
+                timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rqb), dim3(256), 0, st, rr); });
+                if (g_prof_on) {
+                    std::lock_guard<std::mutex> g(g_prof_mu);
+                    g_ctr.requests += nrep;
+                }
+            }
+            // reads that need more seeds go to the next pass
+            if (!final_pass) {
+                HIP_OK(select_idx(sel_tmp, sel_tb, nr, FlagPred{rflag, RF_PENDING}, pend_local, sel_n + 3, st));
+                hipLaunchKernelGGL(k_map_gid, dim3(256), dim3(256), 0, st, pend_local, sel_n + 3, ps, pending_out + pend_count);
+                int64_t np = 0;
+                HIP_OK(hipMemcpyAsync(&np, sel_n + 3, 8, hipMemcpyDeviceToHost, st));
+                HIP_OK(hipStreamSynchronize(st));
+                pend_count += np;
             }
             HIP_OK(hipGetLastError());
             if (g_prof_on) {
@@ -1831,11 +1976,12 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         return SNAP_OK;
     };
 
-    // stage 1 (when it is not complete): the first pass1_seeds seeds, limit
-    // pass1_limit; final stage: every seed. In the final stage, short reads'
-    // locations are verified first with limit final_limit and, for reads whose
-    // replay needs more, again with the full limit; long reads' locations are
-    // verified on request with the exact limit.
+    // stage 1 (when it is not complete): the first pass1_seeds seeds, locations
+    // verified first with limit pass1_limit; final stage: every seed, first limit
+    // final_limit. In both, the replay asks for whatever more it needs (short reads:
+    // their undecided locations at the full limit; long reads in the final stage:
+    // single locations at the exact limit) and only reads that need more seeds
+    // leave stage 1.
     struct Stage { int seeds, cap; };
     Stage stages[2];
     int nst = 0;
@@ -1846,23 +1992,18 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int kf = tune.final_limit > 0 && tune.final_limit < Kmax ? tune.final_limit : KCAP_NONE;
         stages[nst++] = Stage{NS, kf};
     }
-    unsigned long long *npend[2] = {npending, npending + 1};
     uint32_t *plist[2] = {pending, pending + n_reads};
     const uint32_t *list = nullptr;
     int64_t list_len = n_reads;
     for (int k = 0; k < nst && list_len > 0; k++) {
         const bool last = (k == nst - 1);
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)npend[k & 1], 2, 0u);
         pending_out = plist[k & 1];
-        npending_out = npend[k & 1];
+        pend_count = 0;
         int rc = run_pass(list, list_len, stages[k].seeds, stages[k].cap, last ? 1 : 0);
         if (rc != SNAP_OK) return rc;
         if (last) break;
-        unsigned long long np = 0;
-        HIP_OK(hipMemcpyAsync(&np, npend[k & 1], 8, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
         list = plist[k & 1];
-        list_len = (int64_t)np;
+        list_len = pend_count;
     }
     return SNAP_OK;
 }

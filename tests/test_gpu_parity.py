@@ -140,9 +140,10 @@ def test_small_workspace_many_passes(snapgpu, oracle_mod, synth_mod):
 
 
 @pytest.mark.parametrize("seeds,limit,limit2", [(0, 0, 0), (1, 1, 0), (2, 0, 0), (3, 2, 5), (4, 4, 0), (4, 3, 7),
-                                               (6, 8, 9), (32, 63, 0), (1, 0, 3)])
+                                               (6, 8, 9), (32, 63, 0), (1, 0, 3), (6, 4, 4), (6, 1, 1), (0, 2, 2),
+                                               (8, 3, 3)])
 def test_pass_schedule_invariance(snapgpu, oracle_mod, synth_mod, seeds, limit, limit2):
-    """The pass schedule (stage seeds and verify limits) never changes outputs."""
+    """The pass schedule (stage seeds and first verify limits) never changes outputs."""
     from synth.workloads import MID
     w, g, reads = _world(synth_mod, MID, 1_000_000, 6_000)
     old = snapgpu.get_tuning()
