@@ -167,6 +167,8 @@ typedef struct {
     int32_t final_limit;
     int32_t lane_max_len;   /* verify tile: reads up to this length (and limits up to 63) get one lane
                                per location, longer ones a wave per location; 0 = 512 (the maximum) */
+    int32_t exact_rounds;   /* lane-tile reads ask for single locations at the exact limit in this many
+                               replay rounds, then for all their undecided locations at the full limit */
 } snap_tuning;
 
 int snap_set_tuning(const snap_tuning *t);

@@ -45,19 +45,34 @@ class KernelTime(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "final_limit", "lane_max_len")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "final_limit", "lane_max_len",
+                                               "exact_rounds")]
 
     def astuple(self):
         return tuple(int(getattr(self, n)) for n, _ in self._fields_)
 
 
-def set_tuning(pass1_seeds: int, pass1_limit: int, final_limit: int = 0, lane_max_len: int = 0):
+DEFAULT_EXACT_ROUNDS = 2
+
+
+def make_tuning(t) -> "Tuning":
+    """A Tuning from a Tuning or a tuple of its fields (exact_rounds may be left out)."""
+    if isinstance(t, Tuning):
+        return t
+    t = tuple(int(x) for x in t)
+    if len(t) == 4:
+        t = t + (DEFAULT_EXACT_ROUNDS,)
+    return Tuning(*t)
+
+
+def set_tuning(pass1_seeds: int, pass1_limit: int, final_limit: int = 0, lane_max_len: int = 0,
+               exact_rounds: int = DEFAULT_EXACT_ROUNDS):
     """Output-invariant pass schedule and verify tiling (see snap_set_tuning); 0 = no cap."""
-    _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, final_limit, lane_max_len))),
-           "snap_set_tuning")
+    _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, final_limit, lane_max_len,
+                                                     exact_rounds))), "snap_set_tuning")
 
 
-def get_tuning() -> tuple[int, int, int, int]:
+def get_tuning() -> tuple[int, int, int, int, int]:
     t = Tuning()
     _check(lib().snap_get_tuning(ctypes.byref(t)), "snap_get_tuning")
     return t.astuple()
@@ -262,7 +277,7 @@ def align(index: Index, reads, lengths, d_max: int, params: Params | None = None
         workspace = torch.empty(max(wb, 256), dtype=torch.uint8, device=dev)
     if batched:
         if isinstance(tuning, tuple):
-            tuning = Tuning(*tuning)
+            tuning = make_tuning(tuning)
         tp = ctypes.byref(tuning) if tuning is not None else None
         code = lib().snap_align_batched(index.handle, reads.data_ptr(), lengths.data_ptr(), n, d_max,
                                         ctypes.byref(params), tp, out.pos.data_ptr(), out.strand.data_ptr(),
@@ -317,7 +332,7 @@ class Server:
         self.cfg = server_config(d_max=d_max, **cfg)
         tp = None
         if tuning is not None:
-            tp = ctypes.byref(Tuning(*tuning) if isinstance(tuning, tuple) else tuning)
+            tp = ctypes.byref(make_tuning(tuning))
         h = ctypes.c_void_p()
         _check(lib().snap_server_create(index.handle, ctypes.byref(self.params), ctypes.byref(self.cfg), tp,
                                         ctypes.byref(h)), "snap_server_create")

@@ -2,7 +2,8 @@
 
 The knobs (snap_tuning): the seeds and verify limit of the first pass, the first
 verify limit of the final pass, the verify tile bound (reads up to that length
-get one lane per location, longer ones a wave per location). Outputs do
+get one lane per location, longer ones a wave per location) and the number of
+replay rounds that ask for single locations. Outputs do
 not depend on them; only the time does. The tuner aligns a sample of the batch
 with each candidate, keeps the fastest, and records it in a JSON table keyed by
 the batch's read-length class.
@@ -15,25 +16,26 @@ import time
 
 import numpy as np
 
-from . import Tuning, align, default_params
+from . import align, default_params, make_tuning
 
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_table.json")
 
-# (pass1_seeds, pass1_limit, final_limit, lane_max_len); 0 = no cap / default
+# (pass1_seeds, pass1_limit, final_limit, lane_max_len, exact_rounds); 0 = no cap / default
 CANDIDATES = [
-    (0, 0, 0, 0),
-    (0, 3, 3, 0),
-    (6, 0, 0, 0),
-    (6, 2, 2, 0),
-    (6, 3, 3, 0),
-    (6, 4, 4, 0),
-    (6, 5, 5, 0),
-    (4, 3, 3, 0),
-    (4, 4, 4, 0),
-    (8, 3, 3, 0),
-    (8, 4, 4, 0),
-    (6, 4, 4, 256),
-    (6, 4, 4, 128),
+    (0, 0, 0, 0, 2),
+    (6, 0, 0, 0, 2),
+    (4, 4, 4, 0, 2),
+    (4, 5, 5, 0, 1),
+    (5, 4, 4, 0, 1),
+    (5, 5, 5, 0, 0),
+    (5, 5, 5, 0, 1),
+    (5, 5, 5, 0, 2),
+    (5, 6, 6, 0, 1),
+    (6, 4, 4, 0, 2),
+    (6, 5, 5, 0, 1),
+    (6, 6, 6, 0, 1),
+    (5, 5, 5, 256, 1),
+    (5, 5, 5, 128, 1),
 ]
 
 
@@ -76,7 +78,7 @@ def tune(index, reads_dev, lengths_dev, d_max: int, params=None, batched: bool =
     timings = {}
     stream = torch.cuda.current_stream()
     for cand in candidates:
-        tp = Tuning(*cand)
+        tp = make_tuning(cand)
         out = align(index, rb, ln, d_max, params, out=out, max_len=max_len, batched=True, tuning=tp) \
             if batched else _plain(index, rb, ln, d_max, params, out, max_len, cand)
         torch.cuda.synchronize()

@@ -53,10 +53,11 @@ constexpr int LANE_LMAX = 512;
 // wave tile when the read is verified a wave per location; -1 = none.
 constexpr int REQ_WAVE = 0x4000;
 constexpr int REQ_LIMIT_MASK = 0x3FFF;
-// A short read's replay asks for single locations at exactly the limit it uses for
-// this many rounds; after that for every undecided location at the full limit.
-constexpr int REQ_EXACT_ROUNDS = 3;
 constexpr uint32_t REQ_WAVE_READ = 0x80000000u;
+// Replay of reads with more than 64 locations: up to this many are staged in LDS
+// (seed mask, capped distance | verified limit, scored bit), per wave.
+constexpr int HEAVY_LDS_LOCS = 1024;
+constexpr int HEAVY_LDS_WORDS = 2 * HEAVY_LDS_LOCS + HEAVY_LDS_LOCS / 32;
 // Outcome of a read's replay in a pass.
 constexpr uint8_t RF_DONE = 0;      // outputs written
 constexpr uint8_t RF_PENDING = 1;   // needs a seed this pass did not probe
@@ -1062,6 +1063,7 @@ struct ReplayArgs {
     const uint32_t *rlist;      // chunk reads to replay (null: all nr)
     const int64_t *rlist_n;
     int32_t round;              // 0 for the first replay of the chunk, then 1, 2, ...
+    int32_t exact_rounds;       // short reads ask for single locations in rounds below this
     int32_t lane_lmax;          // reads up to this length (limit <= 63) are verified one lane per location
     int64_t *pos;
     int8_t *strand;
@@ -1106,6 +1108,27 @@ __device__ inline void state_update(ReadState &st, int64_t rep, int vd, int64_t 
     }
 }
 
+// A register's value in lane l, l the same in every lane: a scalar read of one lane
+// (no LDS round trip, unlike a shuffle).
+__device__ inline int lane_i32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline uint64_t lane_u64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The lowest lane holding the largest v (0 <= v < 64, 0 = no candidate), or -1:
+// one ballot per bit from the top, keeping the lanes that have it.
+__device__ inline int wave_argmax6(uint32_t v) {
+    uint64_t alive = __ballot(v != 0);
+    if (!alive) return -1;
+    for (int b = 5; b >= 0; b--) {
+        const uint64_t hb = alive & __ballot((v >> b) & 1u);
+        if (hb) alive = hb;
+    }
+    return __builtin_ctzll(alive);
+}
+
 // A read's verification requests: the locations whose `want` is set (all lanes of
 // the wave call this together), each with limit `code`, listed at the read's first
 // location slot.
@@ -1141,13 +1164,11 @@ __device__ inline void heavy_request(const ReplayArgs &a, int64_t base, int64_t 
 // seed mask, capped distance, verified limit, scored flag, bucket minimum when k is
 // its bucket's representative), so the replay runs on shuffles and ballots.
 __device__ inline void light_record(int j, int d, ReadState &st, uint64_t key, int rep, uint64_t &bmin, int lane) {
-    const uint32_t klo = __shfl((unsigned)(uint32_t)key, j, 64), khi = __shfl((unsigned)(uint32_t)(key >> 32), j, 64);
-    const uint64_t kj = ((uint64_t)khi << 32) | klo;
+    const uint64_t kj = lane_u64(key, j);
     const int64_t p = (int64_t)(kj >> 1);
     const int s = (int)(kj & 1);
-    const int rj = __shfl(rep, j, 64);
-    const uint32_t blo = __shfl((unsigned)(uint32_t)bmin, rj, 64), bhi = __shfl((unsigned)(uint32_t)(bmin >> 32), rj, 64);
-    const uint64_t bv = ((uint64_t)bhi << 32) | blo;
+    const int rj = lane_i32(rep, j);
+    const uint64_t bv = lane_u64(bmin, rj);
     const uint64_t nv0 = ((uint64_t)d << 32) | (uint64_t)p;
     const uint64_t nv = nv0 < bv ? nv0 : bv;
     if (lane == rj) bmin = nv;
@@ -1187,13 +1208,6 @@ __device__ inline void wave_record(const ReplayArgs &a, int64_t base, int64_t k,
 }
 
 
-__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
-    for (int d = 32; d >= 1; d >>= 1) {
-        const unsigned long long o = shfl_xor64(v, d);
-        v = o > v ? o : v;
-    }
-    return v;
-}
 
 // EditDistance(Read, Reference[p_k], lim) from what is known about location k: its
 // capped distance dc = min(D, vl + 1) for the limit vl it was verified with.
@@ -1217,29 +1231,34 @@ __device__ inline int ed_answer(int dc, int vl, int lim) {
 // location only changes state at calls that return a distance, so it scans for the
 // next such location in selection order (vote count descending, then p, then
 // strand) instead of visiting each one.
+// LIGHT: the reads with at most 64 locations (registers); otherwise the others
+// (global memory). Both instantiations run over the same read list.
+template <bool LIGHT>
 __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
+    extern __shared__ uint32_t rsm[];   // heavy instantiation: HEAVY_LDS_WORDS per wave
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t nlist = a.rlist ? *a.rlist_n : a.ps.nr;
     for (int64_t ri = wave; ri < nlist; ri += nwaves) {
         const int64_t r = a.rlist ? (int64_t)a.rlist[ri] : ri;
+        const int64_t C = a.count[r];
+        if (LIGHT != (C <= 64)) continue;
         const int64_t g = gid(a.ps, r);
         const int L = a.len[g];
         const int dmax = dmax_for_length(a.rule, L), c = a.rule.c;
         const int NS = a.ps.NS;
         const int64_t base = a.coff[r];
-        const int64_t C = a.count[r];
         const int Kfull = dmax + c - 1;
         const bool lane_class = L <= a.lane_lmax && Kfull <= LANE_KMAX;
-        const bool all_undecided = lane_class && a.round >= REQ_EXACT_ROUNDS;
+        const bool all_undecided = lane_class && a.round >= a.exact_rounds;
         ReadState st{DINF, DINF, -1, -1, -1};
         const int round0 = L / a.rule.s;
         int t = 0, call = -1;
         bool looked = false, all_over = true, ended = false, unresolved = false;
         int64_t need_k = -1;
         uint32_t prefix = 0;
-        if (C <= 64) {
+        if constexpr (LIGHT) {
             // ---- registers: location `lane`
             const bool have = lane < C;
             const uint64_t key = have ? a.key[base + lane] : ~0ull;
@@ -1263,7 +1282,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             const uint64_t range = upto & ~((1ull << run0) - 1);
             const int rep = __builtin_ctzll(mine & range);
             for (int i = 0; i < NS; i++) {
-                const int status = __shfl(stat, i, 64);
+                const int status = lane_i32(stat, i);
                 if (status == ST_NONE) { ended = true; break; }
                 if (status == ST_N) continue;
                 looked = true;
@@ -1272,14 +1291,10 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                 prefix |= 1u << i;
                 if (i < round0) t++;
                 const uint32_t m = mask & prefix;
-                unsigned long long v = (have && m && !scored)
-                    ? ((unsigned long long)__builtin_popcount(m) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)lane)
-                    : 0ull;
-                v = wave_max_u64(v);
-                if (v) {
-                    const int kb = (int)(0xFFFFFFFFu - (uint32_t)(v & 0xFFFFFFFFull));
+                const int kb = wave_argmax6((have && m && !scored) ? (uint32_t)__builtin_popcount(m) : 0u);
+                if (kb >= 0) {
                     const int lim = d_limit(st, dmax, c);
-                    const int res = ed_answer(__shfl(dc, kb, 64), __shfl(vl, kb, 64), lim);
+                    const int res = ed_answer(lane_i32(dc, kb), lane_i32(vl, kb), lim);
                     if (res == -2) {
                         unresolved = true;
                         need_k = kb;
@@ -1318,7 +1333,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                                 }
                                 break;
                             }
-                            light_record(j, __shfl(res, j, 64), st, key, rep, bmin, lane);
+                            light_record(j, lane_i32(res, j), st, key, rep, bmin, lane);
                             if (lane <= j) in = false;
                         }
                     }
@@ -1327,10 +1342,29 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                 }
             }
         } else {
-        for (int64_t k = lane; k < C; k += 64) {
-            a.scored[base + k] = 0;
-            a.bmin[base + k] = ~0ull;
+        // ---- reads with more than 64 locations: seed masks, capped distances, limits
+        // and scored flags staged in this wave's LDS when they fit, else read in place
+        const bool in_lds = C <= HEAVY_LDS_LOCS;
+        uint32_t *Lmask = rsm + (threadIdx.x >> 6) * HEAVY_LDS_WORDS;
+        uint32_t *Ldv = Lmask + HEAVY_LDS_LOCS;
+        uint32_t *Lsc = Ldv + HEAVY_LDS_LOCS;
+        if (in_lds) {
+            for (int64_t k = lane; k < C; k += 64) {
+                Lmask[k] = a.mask[base + k];
+                Ldv[k] = (uint32_t)a.dcap[base + k] | ((uint32_t)(uint16_t)a.vlim[base + k] << 16);
+            }
+            for (int w = lane; w < HEAVY_LDS_LOCS / 32; w += 64) Lsc[w] = 0;
+        } else {
+            for (int64_t k = lane; k < C; k += 64) a.scored[base + k] = 0;
         }
+        for (int64_t k = lane; k < C; k += 64) a.bmin[base + k] = ~0ull;
+        __builtin_amdgcn_wave_barrier();
+        auto mask_at = [&](int64_t k) -> uint32_t { return in_lds ? Lmask[k] : a.mask[base + k]; };
+        auto dc_at = [&](int64_t k) -> int { return in_lds ? (int)(Ldv[k] & 0xFFFFu) : (int)a.dcap[base + k]; };
+        auto vl_at = [&](int64_t k) -> int { return in_lds ? (int)(int16_t)(Ldv[k] >> 16) : (int)a.vlim[base + k]; };
+        auto scored_at = [&](int64_t k) -> bool {
+            return in_lds ? ((Lsc[k >> 5] >> (k & 31)) & 1u) != 0 : a.scored[base + k] != 0;
+        };
         for (int i = 0; i < NS; i++) {
             const int status = a.pr[r * NS + i].status;
             if (status == ST_NONE) { ended = true; break; }
@@ -1341,25 +1375,27 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             prefix |= 1u << i;
             if (i < round0) t++;
             // the unscored location with the most seeds hitting; ties to smaller p, then +
-            unsigned long long best = 0;
-            for (int64_t k = lane; k < C; k += 64) {
-                const uint32_t m = a.mask[base + k] & prefix;
-                if (!m || a.scored[base + k]) continue;
-                const unsigned long long v = ((unsigned long long)__builtin_popcount(m) << 32) |
-                                             (unsigned long long)(0xFFFFFFFFu - (uint32_t)k);
-                best = v > best ? v : best;
+            int64_t kb = -1;
+            uint32_t bv = 0;
+            for (int64_t c0 = 0; c0 < C; c0 += 64) {
+                const int64_t k = c0 + lane;
+                uint32_t v = 0;
+                if (k < C && !scored_at(k)) v = (uint32_t)__builtin_popcount(mask_at(k) & prefix);
+                const int j = wave_argmax6(v);
+                if (j >= 0) {
+                    const uint32_t vj = (uint32_t)lane_i32((int)v, j);
+                    if (vj > bv) { bv = vj; kb = c0 + j; }
+                }
             }
-            best = wave_max_u64(best);
-            if (best) {
-                const int64_t kb = (int64_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+            if (kb >= 0) {
                 const int lim = d_limit(st, dmax, c);
-                const int res = ed_answer(a.dcap[base + kb], a.vlim[base + kb], lim);
+                const int res = ed_answer(dc_at(kb), vl_at(kb), lim);
                 if (res == -2) {
                     unresolved = true;
                     need_k = kb;
                     if (all_undecided) {
                         heavy_request(a, base, C, r, [&](int64_t k) {
-                            const int dck = a.dcap[base + k], vlk = a.vlim[base + k];
+                            const int dck = dc_at(k), vlk = vl_at(k);
                             return dck > vlk && vlk < Kfull;
                         }, Kfull, false, lane);
                     } else {
@@ -1368,7 +1404,11 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                     }
                     break;
                 }
-                if (lane == 0) a.scored[base + kb] = 1;
+                if (lane == 0) {
+                    if (in_lds) Lsc[kb >> 5] |= 1u << (kb & 31);
+                    else a.scored[base + kb] = 1;
+                }
+                __builtin_amdgcn_wave_barrier();
                 if (res >= 0) wave_record(a, base, kb, res, st, lane);
             }
             if (st.d_best < c && st.d_second < st.d_best + c) {
@@ -1383,10 +1423,10 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                         const int64_t k = c0 + lane;
                         bool in = false;
                         int dc = 0, vl = 0;
-                        if (k < C && !a.scored[base + k] && __builtin_popcount(a.mask[base + k] & prefix) == lev) {
+                        if (k < C && !scored_at(k) && __builtin_popcount(mask_at(k) & prefix) == lev) {
                             in = true;
-                            dc = a.dcap[base + k];
-                            vl = a.vlim[base + k];
+                            dc = dc_at(k);
+                            vl = vl_at(k);
                         }
                         for (;;) {
                             const int lim = d_limit(st, dmax, c);
@@ -1401,8 +1441,8 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                                 if (lane_class) {
                                     const int lr = all_undecided ? Kfull : lim;
                                     heavy_request(a, base, C, r, [&](int64_t k2) {
-                                        const int dck = a.dcap[base + k2], vlk = a.vlim[base + k2];
-                                        return !a.scored[base + k2] && (a.mask[base + k2] & prefix) && dck > vlk && vlk < lr;
+                                        const int dck = dc_at(k2), vlk = vl_at(k2);
+                                        return !scored_at(k2) && (mask_at(k2) & prefix) && dck > vlk && vlk < lr;
                                     }, lr, false, lane);
                                 } else {
                                     const int64_t kq = c0 + j;
@@ -1410,7 +1450,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                                 }
                                 break;
                             }
-                            const int dj = __shfl(res, j, 64);
+                            const int dj = lane_i32(res, j);
                             wave_record(a, base, c0 + j, dj, st, lane);
                             // the calls before j returned the special value: scored, no effect
                             if (lane <= j) in = false;
@@ -1495,10 +1535,28 @@ hipError_t select_idx(void *tmp, size_t &tmp_bytes, int64_t items, P pred, uint3
     return hipcub::DeviceSelect::If(tmp, tmp_bytes, ci, out, nsel, (int)items, pred, st);
 }
 
+// Entries of a read list (or reads [0, items) when it is null) with more than 64 locations.
+struct ListAt {
+    const uint32_t *list;
+    __host__ __device__ uint32_t operator()(uint32_t i) const { return list ? list[i] : i; }
+};
+struct HeavyPred {
+    const uint32_t *count;
+    __host__ __device__ bool operator()(uint32_t r) const { return count[r] > 64; }
+};
+
+hipError_t select_heavy(void *tmp, size_t &tmp_bytes, int64_t items, const uint32_t *list, const uint32_t *count,
+                        uint32_t *out, int64_t *nsel, hipStream_t st) {
+    hipcub::CountingInputIterator<uint32_t> ci(0);
+    hipcub::TransformInputIterator<uint32_t, ListAt, hipcub::CountingInputIterator<uint32_t>> it(ci, ListAt{list});
+    return hipcub::DeviceSelect::If(tmp, tmp_bytes, it, out, nsel, (int)items, HeavyPred{count}, st);
+}
+
 size_t select_tmp_bytes(int64_t items) {
-    size_t b = 0;
-    (void)select_idx(nullptr, b, items, FlagPred{nullptr, 0}, nullptr, nullptr, 0);
-    return b;
+    size_t a = 0, b = 0;
+    (void)select_idx(nullptr, a, items, FlagPred{nullptr, 0}, nullptr, nullptr, 0);
+    (void)select_heavy(nullptr, b, items, nullptr, nullptr, nullptr, nullptr, 0);
+    return std::max(a, b);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1594,7 +1652,8 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {6, 4, 4, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound
+snap_tuning g_tune = {6, 4, 4, 0, 2};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
+                                        // exact-request rounds
 
 constexpr int KCAP_NONE = 1 << 20;
 
@@ -1609,7 +1668,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -1650,8 +1709,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
-    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0) return SNAP_EINVAL;
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0) return SNAP_EINVAL;
     const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
+    const int exact_rounds = tune.exact_rounds;
     int dev = 0, lds_max = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1723,6 +1783,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     uint32_t *replay_list = (uint32_t *)(ws + align256(l.off_req + (size_t)R));
     uint32_t *pend_local = replay_list + R;
     uint32_t *reqcount = pend_local + R;
+    uint32_t *heavy_list = pend_local;   // free while a pass replays (the next-pass list is made after)
     int64_t *req_off = (int64_t *)(ws + align256(l.off_req + (size_t)R) + align256(3 * sizeof(uint32_t) * (size_t)R));
     const int64_t PS = l.pool_slots;
     char *pool = ws + l.off_pool;
@@ -1886,9 +1947,22 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
-                          rflag, rq, short_list, reqcount, nullptr, nullptr, 0, lane_lmax, pos, strand, dist, second, call};
+                          rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax, pos, strand,
+                          dist, second, call};
             const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
-            timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rb), dim3(256), 0, st, ra); });
+            // reads with more than 64 locations replay from their own list
+            auto replay = [&](const ReplayArgs &x, unsigned blocks, int64_t items) {
+                timed("replay", st, [&] { hipLaunchKernelGGL(k_replay<true>, dim3(blocks), dim3(256), 0, st, x); });
+                if (maxH > 64) {
+                    (void)select_heavy(sel_tmp, sel_tb, items, x.rlist, ccount, heavy_list, sel_n + 4, st);
+                    ReplayArgs h = x;
+                    h.rlist = heavy_list;
+                    h.rlist_n = sel_n + 4;
+                    const unsigned hb = (unsigned)std::min<int64_t>((items + 3) / 4, 1024);
+                    timed("replay_heavy", st, [&] { hipLaunchKernelGGL(k_replay<false>, dim3(hb), dim3(256), (size_t)4 * 4 * HEAVY_LDS_WORDS, st, h); });
+                }
+            };
+            replay(ra, rb, nr);
             // verify what the replays asked for, replay those reads, until nothing is asked
             for (int round = 1;; round++) {
                 int64_t nrep = 0;
@@ -1935,7 +2009,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 rr.rlist_n = sel_n + 2;
                 rr.round = round;
                 const unsigned rqb = (unsigned)std::min<int64_t>((nrep + 3) / 4, 8192);
-                timed("replay", st, [&] { hipLaunchKernelGGL(k_replay, dim3(rqb), dim3(256), 0, st, rr); });
+                replay(rr, rqb, nrep);
                 if (g_prof_on) {
                     std::lock_guard<std::mutex> g(g_prof_mu);
                     g_ctr.requests += nrep;

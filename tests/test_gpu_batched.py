@@ -53,7 +53,7 @@ def test_batched_vs_oracle(snapgpu, oracle_mod, mixed):
 
 
 @pytest.mark.parametrize("tuning", [(0, 0, 0, 0), (4, 4, 0, 0), (2, 3, 8, 128), (6, 10, 40, 512), (1, 1, 0, 64),
-                                    (3, 0, 0, 300)])
+                                    (3, 0, 0, 300), (6, 3, 3, 0, 0), (6, 2, 2, 256, 1)])
 def test_batched_schedule_and_tile_invariance(snapgpu, mixed, tuning):
     w, g, reads = mixed
     gix = snapgpu.Index(g, 20)
