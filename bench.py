@@ -70,6 +70,24 @@ def roofline_of(kern, ctr, prefer=None):
             "frac": round(achieved / peak, 5), "avg_launch_ms": round(total_ms / launches, 4), "launches": launches}
 
 
+def read_traffic(path, kernel, workload, schedule):
+    """HBM bytes per launch from a counter summary ('key: value' lines, '#' comments),
+    when it covers this kernel, workload and pass schedule; else None."""
+    try:
+        kv = {}
+        for line in open(path):
+            line = line.strip()
+            if line and not line.startswith("#") and ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sched = tuple(int(x) for x in kv.get("schedule", "").split(",") if x.strip())
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and sched == tuple(schedule):
+            return int(kv["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def cpu_baseline(g, reads, w, got, seconds, log_fn=None):
     """The oracle on a seeded sample sized to about `seconds` of CPU time; checks
     the GPU outputs of the sample bit-exact first."""
@@ -177,10 +195,14 @@ def bench_batched(args, w, dev):
     if args.tuning:
         tuning = tuple(int(x) for x in args.tuning.split(","))
     elif not args.no_autotune:
-        tune_info = autotune.tune(gix, rb, ln, d_max, params, batched=True, sample_reads=min(reads.n, 100_000),
-                                  table_path=None, log=log)
+        rec = None if args.retune else autotune.lookup_entry(reads.lengths, batched=True)
+        if rec:
+            tune_info = dict(rec, source="tuning table")
+        else:
+            tune_info = autotune.tune(gix, rb, ln, d_max, params, batched=True, sample_reads=min(reads.n, 100_000),
+                                      table_path=None, log=log)
         tuning = tuple(tune_info["tuning"])
-        log(f"autotuned schedule {tuning}")
+        log(f"schedule {tuning} ({tune_info.get('source', 'autotuned')})")
     wb = snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), ml, d_max, params) * 2
     ws = torch.empty(wb, dtype=torch.uint8, device=dev)
     out = snapgpu.align(gix, rb, ln, d_max, params, workspace=ws, max_len=ml, batched=True, tuning=tuning)
@@ -353,9 +375,12 @@ def main():
     ap.add_argument("--reads", type=int, default=0, help="override the read count (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "verify_traffic_mid.txt"),
+                    help="counter summary giving the dominant kernel's HBM bytes per launch")
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="library default schedule")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner even when the package's tuning table has this length class")
     ap.add_argument("--tuning", default="", help="fixed schedule a,b,c,d (snap_tuning fields); skips the autotuner")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's plain copy kernel over this many bytes, 3 times "
@@ -415,10 +440,14 @@ def main():
         log(f"fixed schedule {snapgpu.get_tuning()}")
     elif not args.no_autotune:
         from paper_1111_5572_amd import autotune
-        tune_info = autotune.tune(gix, rb, ln, w.params.d_max, params, batched=False,
-                                  sample_reads=min(reads.n, 1_000_000), table_path=None, log=log)
+        rec = None if args.retune else autotune.lookup_entry(reads.lengths, batched=False)
+        if rec:
+            tune_info = dict(rec, source="tuning table")
+        else:
+            tune_info = autotune.tune(gix, rb, ln, w.params.d_max, params, batched=False,
+                                      sample_reads=min(reads.n, 1_000_000), table_path=None, log=log)
         snapgpu.set_tuning(*tune_info["tuning"])
-        log(f"autotuned schedule {tuple(tune_info['tuning'])}")
+        log(f"schedule {tuple(tune_info['tuning'])} ({tune_info.get('source', 'autotuned')})")
     out = snapgpu.align(gix, rb, ln, w.params.d_max, params, workspace=ws, max_len=max_len)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -448,38 +477,9 @@ def main():
     got = out.numpy()
     calls = np.bincount(got[4].astype(np.int64), minlength=3)
 
-    # roofline of the dominant kernel
-    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
-    launches, total_ms = kern[dom]
-    avg_s = total_ms / 1000.0 / launches
-    per_launch = 1.0 / launches
-    if dom == "probe":
-        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
-        work = ctr["seed_slots"] * PROBE_BYTES_PER_SLOT * per_launch / 1e9
-    elif dom == "gather":
-        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
-        work = (ctr["seed_slots"] * GATHER_BYTES_PER_SLOT + ctr["hits"] * GATHER_BYTES_PER_HIT) * per_launch / 1e9
-    elif dom.startswith("dedupe"):
-        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
-        work = (ctr["hits"] * DEDUPE_BYTES_PER_HIT + ctr["locations"] * DEDUPE_BYTES_PER_LOC) * per_launch / 1e9
-    elif dom == "verify":
-        bound, unit, peak = "alu", "TOP/s", VALU_PEAK_TOPS
-        work = ctr["lv_steps"] * VERIFY_OPS_PER_STEP * per_launch / 1e12
-    else:
-        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
-        work = float("nan")
-    achieved = work / avg_s
-    traffic = None
-    if os.path.exists(args.traffic):
-        try:
-            tr = json.load(open(args.traffic))
-            if tr.get("kernel") == dom and tr.get("workload") == w.name:
-                traffic = tr.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 5), "traffic": traffic,
-                "avg_launch_ms": round(total_ms / launches, 4), "launches": launches}
+    # roofline of the dominant kernel, with HBM traffic from the committed counter summary
+    roofline = roofline_of(kern, ctr)
+    roofline["traffic"] = read_traffic(args.traffic, roofline["kernel"], w.name, snapgpu.get_tuning())
 
     # CPU oracle on a bounded sample, and a bit-exact check of that sample
     cpu = None

@@ -56,9 +56,17 @@ def load_table(path: str = TABLE_PATH) -> dict:
     return {}
 
 
+def lookup_entry(lengths: np.ndarray, batched: bool, path: str = TABLE_PATH):
+    """The recorded entry (tuning, timings, sample) for this length class, or None."""
+    e = load_table(path).get(("batched:" if batched else "plain:") + length_class(lengths))
+    if e and len(e.get("tuning", ())) == len(CANDIDATES[0]):
+        return e
+    return None
+
+
 def lookup(lengths: np.ndarray, batched: bool, path: str = TABLE_PATH):
     """The recorded tuning for this length class, or None."""
-    e = load_table(path).get(("batched:" if batched else "plain:") + length_class(lengths))
+    e = lookup_entry(lengths, batched, path)
     return tuple(e["tuning"]) if e else None
 
 

@@ -733,12 +733,25 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
 
 
 template <int KMAX>
-__global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
-    extern __shared__ uint32_t sm[];
+__device__ inline void verify_lanes(const VerifyArgs &a, uint32_t *sm) {
     const int lane = threadIdx.x;
     const int64_t n = a.list ? *a.nlist_ptr : *a.ncand_ptr;
     for (int64_t idx = (int64_t)blockIdx.x * 64 + lane; idx < n; idx += (int64_t)gridDim.x * 64)
         verify_lane<KMAX>(a, a.list ? (int64_t)a.list[idx] : idx, sm);
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_verify(VerifyArgs a) {
+    extern __shared__ uint32_t sm[];
+    verify_lanes<KMAX>(a, sm);
+}
+
+// The same lane tile over the locations replays asked for (each at its requested
+// limit); a kernel of its own so that profiles tell the two apart.
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_verify_requested(VerifyArgs a) {
+    extern __shared__ uint32_t sm[];
+    verify_lanes<KMAX>(a, sm);
 }
 
 // Locations whose read or limit is too large for one lane: one wave per location.
@@ -1988,11 +2001,11 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     const unsigned vb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)cus * 16));
                     timed("verify_request", st, [&] {
                         if (kmf == 15)
-                            hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), ldsf, st, vq);
+                            hipLaunchKernelGGL(k_verify_requested<15>, dim3(vb), dim3(64), ldsf, st, vq);
                         else if (kmf == 31)
-                            hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), ldsf, st, vq);
+                            hipLaunchKernelGGL(k_verify_requested<31>, dim3(vb), dim3(64), ldsf, st, vq);
                         else
-                            hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), ldsf, st, vq);
+                            hipLaunchKernelGGL(k_verify_requested<63>, dim3(vb), dim3(64), ldsf, st, vq);
                     });
                 }
                 if (!all_lane) {
