@@ -270,8 +270,15 @@ def bench_served(args, w, dev):
     gix = snapgpu.Index(g, w.params.seed_len)
     log(f"index resident in {time.time() - t:.1f}s")
     params = snapgpu.params_from(w.params)
-    srv = snapgpu.Server(gix, w.params.d_max, params, slots=4, batch_reads=1 << 16, batch_bases=160 << 20,
-                         hbm_budget=48 << 30, max_waiting=1 << 14)
+    # the batched form's schedule for this length mix, when the tuning table has it
+    from paper_1111_5572_amd import autotune
+    if args.tuning:
+        tuning = tuple(int(x) for x in args.tuning.split(","))
+    else:
+        tuning = None if args.no_autotune else autotune.lookup(pool.lengths, batched=True)
+    log(f"server schedule: {tuning or 'library default'}")
+    srv = snapgpu.Server(gix, w.params.d_max, params, tuning=tuning, slots=4, batch_reads=1 << 16,
+                         batch_bases=160 << 20, hbm_budget=48 << 30, max_waiting=1 << 14)
     log(f"server: {srv.stats()}")
 
     offs = pool.offsets

@@ -1234,16 +1234,16 @@ __device__ inline int ed_answer(int dc, int vl, int lim) {
 // one wave per read. A call is answered from the location's capped distance; when
 // that does not decide it (the location was verified with a limit below the one
 // Algorithm 1 asks for), the read records a verification request and is replayed
-// once it is answered. A short read (lane tile) asks for that location at exactly
-// that limit in its first rounds, for every location it has not decided at the
-// full limit after that, and, in the phase that scores every remaining location,
-// for every remaining undecided location at the current limit (the limit only
-// shrinks as results come in, up to rare steps of one); a long read always asks for
-// the single location at the exact limit. A read that needs a seed this pass did
-// not probe is left to the next pass. The phase that scores every remaining
-// location only changes state at calls that return a distance, so it scans for the
-// next such location in selection order (vote count descending, then p, then
-// strand) instead of visiting each one.
+// once it is answered. In the main loop a read asks for that one location at
+// exactly that limit (a short read, in the lane tile, does so for its first
+// exact_rounds rounds and then asks for every location it has not decided at the
+// full limit); in the phase that scores every remaining location it asks for
+// every remaining undecided location at the current limit, which only shrinks as
+// results come in (up to rare steps of one, answered by a further round). A read
+// that needs a seed this pass did not probe is left to the next pass. The phase
+// that scores every remaining location only changes state at calls that return a
+// distance, so it scans for the next such location in selection order (vote count
+// descending, then p, then strand) instead of visiting each one.
 // LIGHT: the reads with at most 64 locations (registers); otherwise the others
 // (global memory). Both instantiations run over the same read list.
 template <bool LIGHT>
@@ -1337,13 +1337,10 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                             if ((__ballot(res == -2) >> j) & 1) {
                                 unresolved = true;
                                 need_k = j;
-                                if (lane_class) {
-                                    const int lr = all_undecided ? Kfull : lim;
-                                    light_request(a, base, r, have && !scored && (mask & prefix) && dc > vl && vl < lr,
-                                                  lr, false, lane);
-                                } else {
-                                    light_request(a, base, r, lane == j, REQ_WAVE | lim, true, lane);
-                                }
+                                // every remaining location still undecided at the limit
+                                const int lr = all_undecided ? Kfull : lim;
+                                light_request(a, base, r, have && !scored && (mask & prefix) && dc > vl && vl < lr,
+                                              lane_class ? lr : (REQ_WAVE | lr), !lane_class, lane);
                                 break;
                             }
                             light_record(j, lane_i32(res, j), st, key, rep, bmin, lane);
@@ -1451,16 +1448,12 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                             if ((__ballot(un) >> j) & 1) {
                                 unresolved = true;
                                 need_k = c0 + j;
-                                if (lane_class) {
-                                    const int lr = all_undecided ? Kfull : lim;
-                                    heavy_request(a, base, C, r, [&](int64_t k2) {
-                                        const int dck = dc_at(k2), vlk = vl_at(k2);
-                                        return !scored_at(k2) && (mask_at(k2) & prefix) && dck > vlk && vlk < lr;
-                                    }, lr, false, lane);
-                                } else {
-                                    const int64_t kq = c0 + j;
-                                    heavy_request(a, base, C, r, [&](int64_t k2) { return k2 == kq; }, REQ_WAVE | lim, true, lane);
-                                }
+                                // every remaining location still undecided at the limit
+                                const int lr = all_undecided ? Kfull : lim;
+                                heavy_request(a, base, C, r, [&](int64_t k2) {
+                                    const int dck = dc_at(k2), vlk = vl_at(k2);
+                                    return !scored_at(k2) && (mask_at(k2) & prefix) && dck > vlk && vlk < lr;
+                                }, lane_class ? lr : (REQ_WAVE | lr), !lane_class, lane);
                                 break;
                             }
                             const int dj = lane_i32(res, j);
@@ -1921,9 +1914,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 }
                 VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, ncand,
                               rule, RW, TW, dcap, vlim, steps, slist, nshort};
-                // final pass: long locations are verified on request, with the exact limit
+                // long locations are verified on request, with the exact limit
                 const int64_t *nlong = (const int64_t *)(route_cnt + 1);
-                if (final_pass && !all_lane) {
+                if (!all_lane) {
                     timed("mark", st, [&] { hipLaunchKernelGGL(k_mark_unverified, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, long_list, nlong, dcap, vlim, steps); });
                     nlong = zero_count;
                 }
@@ -1953,10 +1946,6 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                         else
                             hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
                     });
-                    if (!all_lane && !final_pass) {
-                        const unsigned wb = (unsigned)std::min<int64_t>(total, 8192);
-                        timed("verify_wave", st, [&] { hipLaunchKernelGGL(k_verify_wave, dim3(wb), dim3(64), lds_wave, st, wa); });
-                    }
                 }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
