@@ -169,6 +169,9 @@ typedef struct {
                                per location, longer ones a wave per location; 0 = 512 (the maximum) */
     int32_t exact_rounds;   /* lane-tile reads ask for single locations at the exact limit in this many
                                replay rounds, then for all their undecided locations at the full limit */
+    int32_t verify_seeds;   /* snap_align, reads in the lane tile: the first verification covers only
+                               locations hit by one of the first verify_seeds seed slots, the others
+                               are verified when a replay asks (0 = all locations) */
 } snap_tuning;
 
 int snap_set_tuning(const snap_tuning *t);

@@ -46,33 +46,36 @@ class KernelTime(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "final_limit", "lane_max_len",
-                                               "exact_rounds")]
+                                               "exact_rounds", "verify_seeds")]
 
     def astuple(self):
         return tuple(int(getattr(self, n)) for n, _ in self._fields_)
 
 
-DEFAULT_EXACT_ROUNDS = 2
+DEFAULT_EXACT_ROUNDS = 1
 
 
 def make_tuning(t) -> "Tuning":
-    """A Tuning from a Tuning or a tuple of its fields (exact_rounds may be left out)."""
+    """A Tuning from a Tuning or a tuple of its fields (the trailing exact_rounds and
+    verify_seeds may be left out: 1 and 0)."""
     if isinstance(t, Tuning):
         return t
     t = tuple(int(x) for x in t)
     if len(t) == 4:
         t = t + (DEFAULT_EXACT_ROUNDS,)
+    if len(t) == 5:
+        t = t + (0,)
     return Tuning(*t)
 
 
 def set_tuning(pass1_seeds: int, pass1_limit: int, final_limit: int = 0, lane_max_len: int = 0,
-               exact_rounds: int = DEFAULT_EXACT_ROUNDS):
+               exact_rounds: int = DEFAULT_EXACT_ROUNDS, verify_seeds: int = 0):
     """Output-invariant pass schedule and verify tiling (see snap_set_tuning); 0 = no cap."""
     _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, final_limit, lane_max_len,
-                                                     exact_rounds))), "snap_set_tuning")
+                                                     exact_rounds, verify_seeds))), "snap_set_tuning")
 
 
-def get_tuning() -> tuple[int, int, int, int, int]:
+def get_tuning() -> tuple[int, int, int, int, int, int]:
     t = Tuning()
     _check(lib().snap_get_tuning(ctypes.byref(t)), "snap_get_tuning")
     return t.astuple()

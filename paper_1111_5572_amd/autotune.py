@@ -3,7 +3,8 @@
 The knobs (snap_tuning): the seeds and verify limit of the first pass, the first
 verify limit of the final pass, the verify tile bound (reads up to that length
 get one lane per location, longer ones a wave per location) and the number of
-replay rounds that ask for single locations. Outputs do
+replay rounds that ask for single locations, and the seed slots whose locations
+the first verification covers. Outputs do
 not depend on them; only the time does. The tuner aligns a sample of the batch
 with each candidate, keeps the fastest, and records it in a JSON table keyed by
 the batch's read-length class.
@@ -20,22 +21,21 @@ from . import align, default_params, make_tuning
 
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_table.json")
 
-# (pass1_seeds, pass1_limit, final_limit, lane_max_len, exact_rounds); 0 = no cap / default
+# (pass1_seeds, pass1_limit, final_limit, lane_max_len, exact_rounds, verify_seeds); 0 = no cap / default
 CANDIDATES = [
-    (0, 0, 0, 0, 2),
-    (6, 0, 0, 0, 2),
-    (4, 4, 4, 0, 2),
-    (4, 5, 5, 0, 1),
-    (5, 4, 4, 0, 1),
-    (5, 5, 5, 0, 0),
-    (5, 5, 5, 0, 1),
-    (5, 5, 5, 0, 2),
-    (5, 6, 6, 0, 1),
-    (6, 4, 4, 0, 2),
-    (6, 5, 5, 0, 1),
-    (6, 6, 6, 0, 1),
-    (5, 5, 5, 256, 1),
-    (5, 5, 5, 128, 1),
+    (0, 0, 0, 0, 2, 0),
+    (6, 0, 0, 0, 2, 0),
+    (4, 5, 5, 0, 1, 0),
+    (5, 5, 5, 0, 1, 0),
+    (5, 6, 6, 0, 1, 0),
+    (5, 6, 6, 0, 1, 3),
+    (5, 6, 6, 0, 1, 4),
+    (5, 5, 5, 0, 1, 3),
+    (6, 6, 6, 0, 1, 3),
+    (6, 6, 6, 0, 1, 4),
+    (5, 8, 8, 0, 1, 3),
+    (6, 5, 5, 0, 1, 0),
+    (5, 5, 5, 256, 1, 0),
 ]
 
 
@@ -59,7 +59,7 @@ def load_table(path: str = TABLE_PATH) -> dict:
 def lookup_entry(lengths: np.ndarray, batched: bool, path: str = TABLE_PATH):
     """The recorded entry (tuning, timings, sample) for this length class, or None."""
     e = load_table(path).get(("batched:" if batched else "plain:") + length_class(lengths))
-    if e and len(e.get("tuning", ())) == len(CANDIDATES[0]):
+    if e and 4 <= len(e.get("tuning", ())) <= len(CANDIDATES[0]):
         return e
     return None
 

@@ -139,6 +139,19 @@ __device__ inline uint32_t ext_mask16(const uint32_t *a, int64_t x) {
     return funnel(a[w + 1], a[w], (uint32_t)(x & 31)) & 0xFFFFu;
 }
 
+// Whether any of the n >= 1 bits [x, x + n) of a 1-bit array is set (nonzero if so).
+__device__ inline uint32_t any_n(const uint32_t *a, int64_t x, int n) {
+    const int64_t m0 = x >> 5, m1 = (x + n - 1) >> 5;
+    uint32_t acc = 0;
+    for (int64_t m = m0; m <= m1; m++) {
+        uint32_t v = a[m];
+        if (m == m0) v &= 0xFFFFFFFFu << (x & 31);
+        if (m == m1) v &= 0xFFFFFFFFu >> (31 - ((x + n - 1) & 31));
+        acc |= v;
+    }
+    return acc;
+}
+
 // bit k of a 16-bit mask -> bit 2k
 __device__ inline uint32_t spread16(uint32_t m) {
     m = (m | (m << 8)) & 0x00FF00FFu;
@@ -601,26 +614,30 @@ struct VerifyArgs {
 
 // Per-lane LDS arrays are laid out [word][lane], so a wave's accesses to its
 // lanes' arrays hit 64 distinct banks whatever word each lane needs.
+// Only the read' and window codes are staged; the rare read or window that holds
+// an N takes its N flags from the packed 1-bit masks in global memory.
 struct Stage {
-    uint32_t *RC, *RN, *TC, *TN;
+    uint32_t *RC, *TC;
     int16_t *FR;
     int lane;
+    const uint32_t *rmask, *gmask;
+    int64_t xb, p;   // read start in the packed stream, window start in the genome
+    int L, strand;
     __device__ inline uint32_t r16(int i) const {
         int w = i >> 4;
         return funnel(RC[(w + 1) * 64 + lane], RC[w * 64 + lane], (uint32_t)(i & 15) * 2);
-    }
-    __device__ inline uint32_t rn16(int i) const {
-        int w = i >> 4;
-        return funnel(RN[(w + 1) * 64 + lane], RN[w * 64 + lane], (uint32_t)(i & 15) * 2);
     }
     __device__ inline uint32_t t16(int j) const {
         int w = j >> 4;
         return funnel(TC[(w + 1) * 64 + lane], TC[w * 64 + lane], (uint32_t)(j & 15) * 2);
     }
-    __device__ inline uint32_t tn16(int j) const {
-        int w = j >> 4;
-        return funnel(TN[(w + 1) * 64 + lane], TN[w * 64 + lane], (uint32_t)(j & 15) * 2);
+    // N flags of read' bases [i, i + 16) and window bases [j, j + 16), one per 2-bit slot
+    // (bases past the read or the window may carry any value: the caller masks them)
+    __device__ inline uint32_t rn16(int i) const {
+        if (strand == 0) return spread16(ext_mask16(rmask, xb + i));
+        return spread16(__builtin_bitreverse32(ext_mask16(rmask, xb + L - 16 - i)) >> 16);
     }
+    __device__ inline uint32_t tn16(int j) const { return spread16(ext_mask16(gmask, p + j)); }
 };
 
 // Extend a diagonal: from read row i on diagonal d (text column i + d), advance
@@ -682,10 +699,8 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
     Stage st;
     st.lane = lane;
     st.RC = sm;
-    st.RN = st.RC + a.RW * 64;
-    st.TC = st.RN + a.RW * 64;
-    st.TN = st.TC + a.TW * 64;
-    st.FR = reinterpret_cast<int16_t *>(st.TN + a.TW * 64);
+    st.TC = st.RC + a.RW * 64;
+    st.FR = reinterpret_cast<int16_t *>(st.TC + a.TW * 64);
 
     const uint64_t key = a.key[k];
     const int64_t p = (int64_t)(key >> 1);
@@ -696,33 +711,49 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
     const int64_t xb = STREAM_GUARD + a.roff[g];
     const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
 
+    // read' and window, 16 bases per word, each raw word loaded once
     const int nrw = (L + 15) >> 4;
-    uint32_t anyn = 0;
-    for (int w = 0; w < nrw; w++) {
-        uint32_t c, n;
-        if (strand == 0) {
-            c = ext_code16(a.rcode, xb + 16 * w);
-            n = ext_mask16(a.rmask, xb + 16 * w);
-        } else {
-            const int64_t x = xb + L - 16 * (w + 1);
-            c = rc16(ext_code16(a.rcode, x));
-            n = __builtin_bitreverse32(ext_mask16(a.rmask, x)) >> 16;
+    if (strand == 0) {
+        const int64_t q = xb >> 4;
+        const uint32_t sh = (uint32_t)(xb & 15) * 2;
+        uint32_t lo = a.rcode[q];
+        for (int w = 0; w < nrw; w++) {
+            const uint32_t hi = a.rcode[q + w + 1];
+            st.RC[w * 64 + lane] = funnel(hi, lo, sh);
+            lo = hi;
         }
-        anyn |= n;
-        st.RC[w * 64 + lane] = c;
-        st.RN[w * 64 + lane] = spread16(n);
+    } else {
+        // word w of the reverse complement holds bases [xe - 16(w+1), xe - 16w) of the stream
+        const int64_t xe = xb + L;
+        const int64_t q = xe >> 4;
+        const uint32_t sh = (uint32_t)(xe & 15) * 2;
+        uint32_t hi = a.rcode[q];
+        for (int w = 0; w < nrw; w++) {
+            const uint32_t lo = a.rcode[q - w - 1];
+            st.RC[w * 64 + lane] = rc16(funnel(hi, lo, sh));
+            hi = lo;
+        }
     }
     st.RC[nrw * 64 + lane] = 0;
-    st.RN[nrw * 64 + lane] = 0;
     const int ntw = (Tn + 15) >> 4;
-    for (int w = 0; w < ntw; w++) {
-        const uint32_t n = ext_mask16(a.gmask, p + 16 * w);
-        anyn |= n;
-        st.TC[w * 64 + lane] = ext_code16(a.gcode, p + 16 * w);
-        st.TN[w * 64 + lane] = spread16(n);
+    {
+        const int64_t q = p >> 4;
+        const uint32_t sh = (uint32_t)(p & 15) * 2;
+        uint32_t lo = a.gcode[q];
+        for (int w = 0; w < ntw; w++) {
+            const uint32_t hi = a.gcode[q + w + 1];
+            st.TC[w * 64 + lane] = funnel(hi, lo, sh);
+            lo = hi;
+        }
     }
     st.TC[ntw * 64 + lane] = 0;
-    st.TN[ntw * 64 + lane] = 0;
+    const uint32_t anyn = any_n(a.rmask, xb, L) | any_n(a.gmask, p, Tn);
+    st.rmask = a.rmask;
+    st.gmask = a.gmask;
+    st.xb = xb;
+    st.p = p;
+    st.L = L;
+    st.strand = strand;
 
     uint32_t nsteps = 1;
     const int D = anyn ? lv_lane<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane<KMAX, false>(st, L, Tn, K, nsteps);
@@ -997,6 +1028,17 @@ __global__ __launch_bounds__(64) void k_verify_steal(StealArgs a) {
             if (idx < nshort) verify_lane<KMAX>(a.va, (int64_t)a.va.list[idx], ssm);
         }
     }
+}
+
+// Locations hit by none of the first seed slots (`bits`): left for verification on
+// request (capped distance unknown above -1).
+__global__ void k_mark_late(const uint32_t *mask, const int64_t *ncand_ptr, uint32_t bits, uint16_t *dcap,
+                            int16_t *vlim, uint32_t *steps) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= *ncand_ptr || (mask[k] & bits) != 0) return;
+    dcap[k] = 0xFFFF;
+    vlim[k] = -1;
+    if (steps) steps[k] = 0;
 }
 
 // Locations left for verification on request: capped distance unknown above -1.
@@ -1541,6 +1583,14 @@ hipError_t select_idx(void *tmp, size_t &tmp_bytes, int64_t items, P pred, uint3
     return hipcub::DeviceSelect::If(tmp, tmp_bytes, ci, out, nsel, (int)items, pred, st);
 }
 
+// Locations hit by one of the first seed slots (`bits`), below the chunk's location count.
+struct FirstSeedsPred {
+    const uint32_t *mask;
+    const int64_t *ncand;
+    uint32_t bits;
+    __host__ __device__ bool operator()(uint32_t k) const { return (int64_t)k < *ncand && (mask[k] & bits) != 0; }
+};
+
 // Entries of a read list (or reads [0, items) when it is null) with more than 64 locations.
 struct ListAt {
     const uint32_t *list;
@@ -1559,10 +1609,11 @@ hipError_t select_heavy(void *tmp, size_t &tmp_bytes, int64_t items, const uint3
 }
 
 size_t select_tmp_bytes(int64_t items) {
-    size_t a = 0, b = 0;
+    size_t a = 0, b = 0, c = 0;
     (void)select_idx(nullptr, a, items, FlagPred{nullptr, 0}, nullptr, nullptr, 0);
     (void)select_heavy(nullptr, b, items, nullptr, nullptr, nullptr, nullptr, 0);
-    return std::max(a, b);
+    (void)select_idx(nullptr, c, items, FirstSeedsPred{nullptr, nullptr, 0}, nullptr, nullptr, 0);
+    return std::max(a, std::max(b, c));
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1612,7 +1663,7 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     const int64_t minslots = (int64_t)NS * hmax;
     if (pool_slots < minslots) pool_slots = minslots;
     l.pool_slots = pool_slots;
-    l.off_sel = o; o = align256(o + select_tmp_bytes(R + 1));
+    l.off_sel = o; o = align256(o + select_tmp_bytes(std::max<int64_t>(R, pool_slots) + 1));
     l.off_pool = o; o = align256(o + POOL_SLOT_BYTES * (size_t)pool_slots + POOL_ARRAYS * 256);
     l.total = o;
     return l;
@@ -1658,8 +1709,8 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {6, 4, 4, 0, 2};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
-                                        // exact-request rounds
+snap_tuning g_tune = {5, 6, 6, 0, 1, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
+                                        // exact-request rounds, first-verification seeds
 
 constexpr int KCAP_NONE = 1 << 20;
 
@@ -1674,7 +1725,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -1715,9 +1766,10 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
-    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0) return SNAP_EINVAL;
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0) return SNAP_EINVAL;
     const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
     const int exact_rounds = tune.exact_rounds;
+    const int verify_seeds = tune.verify_seeds;
     int dev = 0, lds_max = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1784,7 +1836,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     int64_t *coff = (int64_t *)(ws + l.off_coff);
     void *scan_tmp = ws + l.off_scan;
     void *sel_tmp = ws + l.off_sel;
-    size_t sel_tb = select_tmp_bytes(R + 1);
+    size_t sel_tb = select_tmp_bytes(std::max<int64_t>(R, l.pool_slots) + 1);
     uint8_t *rflag = (uint8_t *)(ws + l.off_req);
     uint32_t *replay_list = (uint32_t *)(ws + align256(l.off_req + (size_t)R));
     uint32_t *pend_local = replay_list + R;
@@ -1835,8 +1887,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const bool all_lane = !batched && maxL <= lane_lmax && Kp <= LANE_KMAX;
         const int RW = (std::max(lane_L, 1) + 15) / 16 + 1;
         const int TW = (std::max(lane_L, 1) + lane_K + 15) / 16 + 1;
-        const int kmax_t = lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63);
-        const size_t lds = (size_t)64 * 4 * (2 * RW + 2 * TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
+        const int kmax_t = lane_K <= 7 ? 7 : (lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63));
+        const size_t lds = (size_t)64 * 4 * (RW + TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
         // wave-per-location tile: any read, any limit (requests go up to the full limit)
         const int Kw = Kmax;
         const int RWL = (std::max(maxL, 1) + 15) / 16 + 1;
@@ -1929,7 +1981,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     StealArgs sa{va, wa, steal_next, nwaves};
                     const size_t lds_s = std::max(lds, lds_wave);
                     timed("verify_steal", st, [&] {
-                        if (kmax_t == 15)
+                        if (kmax_t == 7)
+                            hipLaunchKernelGGL(k_verify_steal<7>, dim3(nwaves), dim3(64), lds_s, st, sa);
+                        else if (kmax_t == 15)
                             hipLaunchKernelGGL(k_verify_steal<15>, dim3(nwaves), dim3(64), lds_s, st, sa);
                         else if (kmax_t == 31)
                             hipLaunchKernelGGL(k_verify_steal<31>, dim3(nwaves), dim3(64), lds_s, st, sa);
@@ -1938,8 +1992,20 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     });
                 } else {
                     const unsigned vb = (unsigned)((total + 63) / 64);
+                    if (all_lane && verify_seeds > 0 && verify_seeds < NSp) {
+                        // first verification only for locations hit by the first seed slots;
+                        // the others wait for a replay to ask
+                        const uint32_t bits = (1u << verify_seeds) - 1u;
+                        const unsigned mb = (unsigned)((total + 255) / 256);
+                        timed("mark", st, [&] { hipLaunchKernelGGL(k_mark_late, dim3(mb), dim3(256), 0, st, mask_c, ncand, bits, dcap, vlim, steps); });
+                        HIP_OK(select_idx(sel_tmp, sel_tb, total, FirstSeedsPred{mask_c, ncand, bits}, short_list, sel_n + 5, st));
+                        va.list = short_list;
+                        va.nlist_ptr = sel_n + 5;
+                    }
                     timed("verify", st, [&] {
-                        if (kmax_t == 15)
+                        if (kmax_t == 7)
+                            hipLaunchKernelGGL(k_verify<7>, dim3(vb), dim3(64), lds, st, va);
+                        else if (kmax_t == 15)
                             hipLaunchKernelGGL(k_verify<15>, dim3(vb), dim3(64), lds, st, va);
                         else if (kmax_t == 31)
                             hipLaunchKernelGGL(k_verify<31>, dim3(vb), dim3(64), lds, st, va);
@@ -1982,14 +2048,16 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     hipLaunchKernelGGL(k_flatten_requests, dim3(fb), dim3(256), 0, st, qa, req_off, long_list);
                     const int kfull = std::min(Kmax, LANE_KMAX);
                     const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
-                    const int kmf = kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63);
-                    const size_t ldsf = (size_t)64 * 4 * (2 * RW + 2 * TWf) + (size_t)64 * 2 * (2 * kmf + 3);
+                    const int kmf = kfull <= 7 ? 7 : (kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63));
+                    const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (size_t)64 * 2 * (2 * kmf + 3);
                     VerifyArgs vq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
                                   coff + nr, rule, RW, TWf, dcap, vlim, steps, long_list, req_off + nrep, rq};
                     // as many waves as fit the device (the count is on the device)
                     const unsigned vb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)cus * 16));
                     timed("verify_request", st, [&] {
-                        if (kmf == 15)
+                        if (kmf == 7)
+                            hipLaunchKernelGGL(k_verify_requested<7>, dim3(vb), dim3(64), ldsf, st, vq);
+                        else if (kmf == 15)
                             hipLaunchKernelGGL(k_verify_requested<15>, dim3(vb), dim3(64), ldsf, st, vq);
                         else if (kmf == 31)
                             hipLaunchKernelGGL(k_verify_requested<31>, dim3(vb), dim3(64), ldsf, st, vq);

@@ -139,18 +139,19 @@ def test_small_workspace_many_passes(snapgpu, oracle_mod, synth_mod):
     assert nbad == 0, rep
 
 
-@pytest.mark.parametrize("seeds,limit,limit2,rounds", [(0, 0, 0, 2), (1, 1, 0, 2), (2, 0, 0, 2), (3, 2, 5, 0),
-                                                      (4, 4, 0, 1), (4, 3, 7, 3), (6, 8, 9, 2), (32, 63, 0, 2),
-                                                      (1, 0, 3, 5), (6, 4, 4, 2), (6, 1, 1, 0), (0, 2, 2, 1),
-                                                      (8, 3, 3, 9), (6, 4, 4, 0)])
-def test_pass_schedule_invariance(snapgpu, oracle_mod, synth_mod, seeds, limit, limit2, rounds):
-    """The pass schedule (stage seeds, first verify limits, exact-request rounds) never changes outputs."""
+@pytest.mark.parametrize("seeds,limit,limit2,rounds,vseeds", [
+    (0, 0, 0, 2, 0), (1, 1, 0, 2, 0), (2, 0, 0, 2, 1), (3, 2, 5, 0, 0), (4, 4, 0, 1, 2), (4, 3, 7, 3, 0),
+    (6, 8, 9, 2, 3), (32, 63, 0, 2, 0), (1, 0, 3, 5, 0), (6, 4, 4, 2, 0), (6, 1, 1, 0, 5), (0, 2, 2, 1, 3),
+    (8, 3, 3, 9, 1), (6, 4, 4, 0, 0), (5, 6, 6, 1, 3), (0, 0, 0, 1, 2)])
+def test_pass_schedule_invariance(snapgpu, oracle_mod, synth_mod, seeds, limit, limit2, rounds, vseeds):
+    """The pass schedule (stage seeds, first verify limits, exact-request rounds, seeds covered by
+    the first verification) never changes outputs."""
     from synth.workloads import MID
     w, g, reads = _world(synth_mod, MID, 1_000_000, 6_000)
     old = snapgpu.get_tuning()
     try:
-        snapgpu.set_tuning(seeds, limit, limit2, 0, rounds)
-        _check(snapgpu, oracle_mod, w, g, reads, f"schedule {seeds}/{limit}/{limit2}/{rounds}")
+        snapgpu.set_tuning(seeds, limit, limit2, 0, rounds, vseeds)
+        _check(snapgpu, oracle_mod, w, g, reads, f"schedule {seeds}/{limit}/{limit2}/{rounds}/{vseeds}")
     finally:
         snapgpu.set_tuning(*old)
 
