@@ -433,6 +433,8 @@ struct DedupeArgs {
     uint32_t *mask;    // the seed slots that voted for each
     uint32_t *count;
     uint32_t *slot_read;   // chunk read of every reserved slot
+    const uint32_t *rlist;     // the reads of this tier (null: every read of the chunk)
+    const int64_t *rlist_n;
 };
 
 __device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
@@ -507,7 +509,10 @@ __global__ __launch_bounds__(NT) void k_dedupe_heavy(DedupeArgs a, uint64_t *gsc
     extern __shared__ uint64_t lds_keys[];
     __shared__ uint32_t wcnt[NT / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int64_t r = blockIdx.x; r < a.nr; r += gridDim.x) {
+    const int64_t n = a.rlist ? *a.rlist_n : a.nr;
+    for (int64_t ri = blockIdx.x; ri < n; ri += gridDim.x) {
+        const int64_t r = a.rlist ? (int64_t)a.rlist[ri] : ri;
+        if (r >= a.nr) continue;
         const uint32_t H = a.hits[r];
         if (H <= lo_h || H > hi_h) continue;
         const int64_t base = a.hoff[r];
@@ -1583,6 +1588,13 @@ hipError_t select_idx(void *tmp, size_t &tmp_bytes, int64_t items, P pred, uint3
     return hipcub::DeviceSelect::If(tmp, tmp_bytes, ci, out, nsel, (int)items, pred, st);
 }
 
+// Reads whose hit count is in (lo, hi].
+struct HitRangePred {
+    const uint32_t *hits;
+    uint32_t lo, hi;
+    __host__ __device__ bool operator()(uint32_t r) const { return hits[r] > lo && hits[r] <= hi; }
+};
+
 // Locations hit by one of the first seed slots (`bits`), below the chunk's location count.
 struct FirstSeedsPred {
     const uint32_t *mask;
@@ -1613,7 +1625,9 @@ size_t select_tmp_bytes(int64_t items) {
     (void)select_idx(nullptr, a, items, FlagPred{nullptr, 0}, nullptr, nullptr, 0);
     (void)select_heavy(nullptr, b, items, nullptr, nullptr, nullptr, nullptr, 0);
     (void)select_idx(nullptr, c, items, FirstSeedsPred{nullptr, nullptr, 0}, nullptr, nullptr, 0);
-    return std::max(a, std::max(b, c));
+    size_t d = 0;
+    (void)select_idx(nullptr, d, items, HitRangePred{nullptr, 0, 0}, nullptr, nullptr, 0);
+    return std::max(std::max(a, d), std::max(b, c));
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1904,12 +1918,16 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             timed("hitcount", st, [&] { hipLaunchKernelGGL(k_hitcount, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, probe, nr, NSp, hits); });
             size_t tb = scan_tmp_bytes(nr + 1);
             HIP_OK(scan_excl(scan_tmp, tb, CastU32{hits, nr}, nr + 1, hoff, st));
-            // total hits and the largest per-read count (one wait per chunk)
+            // total hits, the largest per-read count and the reads of the two sorting
+            // tiers above 64 hits (one wait per chunk)
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)misc, 2, 0u);
             hipLaunchKernelGGL(k_maxlen, dim3(256), dim3(256), 0, st, (const int32_t *)hits, nr, (uint32_t *)misc);
             HIP_OK(hipMemcpyAsync(misc + 1, hoff + nr, 8, hipMemcpyDeviceToDevice, st));
-            int64_t sc[2];
+            HIP_OK(select_idx(sel_tmp, sel_tb, nr, HitRangePred{hits, 64u, 512u}, replay_list, sel_n + 6, st));
+            HIP_OK(select_idx(sel_tmp, sel_tb, nr, HitRangePred{hits, 512u, 0xFFFFFFFFu}, pend_local, sel_n + 7, st));
+            int64_t sc[2], ntier[2];
             HIP_OK(hipMemcpyAsync(sc, misc, 16, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipMemcpyAsync(ntier, sel_n + 6, 16, hipMemcpyDeviceToHost, st));
             HIP_OK(hipStreamSynchronize(st));
             const uint32_t maxH = (uint32_t)(sc[0] & 0x7FFFFFFF);
             int64_t total = sc[1];
@@ -1930,23 +1948,31 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 const unsigned gb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
                 timed("gather", st, [&] { hipLaunchKernelGGL(k_gather, dim3(gb), dim3(256), 0, st, ga); });
             }
-            DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, slot_read};
+            DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, slot_read, nullptr, nullptr};
             {
                 const unsigned lb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
                 timed("dedupe_light", st, [&] { hipLaunchKernelGGL(k_dedupe_light, dim3(lb), dim3(256), 0, st, da); });
             }
-            if (maxH > 64) {
-                // 64 < H <= 512: one wave per read; up to cape: a workgroup; beyond: global scratch
-                const unsigned mb = (unsigned)std::min<int64_t>(nr, 8192);
-                timed("dedupe_medium", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<true, 64>), dim3(mb), dim3(64), (size_t)512 * 8, st, da, key_c, 64u, 512u); });
-                if (maxH > 512) {
-                    const unsigned hb = (unsigned)std::min<int64_t>(nr, 2048);
-                    uint32_t N = 1;
-                    while (N < std::min(maxH, cape)) N <<= 1;
-                    timed("dedupe_heavy", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<true, 256>), dim3(hb), dim3(256), (size_t)N * 8, st, da, key_c, 512u, cape); });
-                    if (maxH > cape)
-                        timed("dedupe_huge", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<false, 256>), dim3(hb), dim3(256), 0, st, da, key_c, cape, 0xFFFFFFFFu); });
-                }
+            // reads beyond 64 hits sort from their own lists (a chunk that shrank to fit the
+            // pool keeps the lists of the whole chunk: the entries past nr are skipped)
+            DedupeArgs dm = da, dh = da;
+            dm.rlist = replay_list;
+            dm.rlist_n = sel_n + 6;
+            dh.rlist = pend_local;
+            dh.rlist_n = sel_n + 7;
+            if (ntier[0] > 0) {
+                // 64 < H <= 512: one wave per read
+                const unsigned mb = (unsigned)std::min<int64_t>(ntier[0], 8192);
+                timed("dedupe_medium", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<true, 64>), dim3(mb), dim3(64), (size_t)512 * 8, st, dm, key_c, 64u, 512u); });
+            }
+            if (ntier[1] > 0) {
+                // up to cape: a workgroup; beyond: global scratch
+                const unsigned hb = (unsigned)std::min<int64_t>(ntier[1], 2048);
+                uint32_t N = 1;
+                while (N < std::min(maxH, cape)) N <<= 1;
+                timed("dedupe_heavy", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<true, 256>), dim3(hb), dim3(256), (size_t)N * 8, st, dh, key_c, 512u, cape); });
+                if (maxH > cape)
+                    timed("dedupe_huge", st, [&] { hipLaunchKernelGGL((k_dedupe_heavy<false, 256>), dim3(hb), dim3(256), 0, st, dh, key_c, cape, 0xFFFFFFFFu); });
             }
             tb = scan_tmp_bytes(nr + 1);
             HIP_OK(scan_excl(scan_tmp, tb, CastU32{ccount, nr}, nr + 1, coff, st));
