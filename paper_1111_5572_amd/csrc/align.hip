@@ -1540,6 +1540,178 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
     }
 }
 
+// Reads with at most TINY_LOCS locations (most reads: a unique region gives one or
+// two): one lane per read, Algorithm 1's control flow run sequentially over
+// registers (the same decisions as the wave paths, in the same order).
+constexpr int TINY_LOCS = 4;
+
+__global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
+    const int64_t nlist = a.rlist ? *a.rlist_n : a.ps.nr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t ri = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ri < nlist; ri += stride) {
+        const int64_t r = a.rlist ? (int64_t)a.rlist[ri] : ri;
+        const int C = (int)a.count[r];
+        if (C > TINY_LOCS) continue;
+        const int64_t g = gid(a.ps, r);
+        const int L = a.len[g];
+        const int dmax = dmax_for_length(a.rule, L), c = a.rule.c;
+        const int NS = a.ps.NS;
+        const int64_t base = a.coff[r];
+        const int Kfull = dmax + c - 1;
+        const bool lane_class = L <= a.lane_lmax && Kfull <= LANE_KMAX;
+        const bool all_undecided = lane_class && a.round >= a.exact_rounds;
+        // location k: p, strand bit, seed mask, capped distance | verified limit << 16;
+        // the bucket minimum is kept at the bucket's representative, the first location
+        // of the same bucket and strand (a 4-bit index per location)
+        uint32_t P[TINY_LOCS], M[TINY_LOCS], DV[TINY_LOCS];
+        uint64_t BM[TINY_LOCS];
+        uint32_t sbits = 0, repw = 0;
+        {
+            uint32_t BK[TINY_LOCS];
+#pragma unroll
+            for (int k = 0; k < TINY_LOCS; k++) {
+                P[k] = 0; M[k] = 0; DV[k] = 0; BK[k] = 0xFFFFFFFFu - (uint32_t)k; BM[k] = ~0ull;
+                if (k < C) {
+                    const uint64_t key = a.key[base + k];
+                    P[k] = (uint32_t)(key >> 1);
+                    sbits |= (uint32_t)(key & 1) << k;
+                    M[k] = a.mask[base + k];
+                    DV[k] = (uint32_t)a.dcap[base + k] | ((uint32_t)(uint16_t)a.vlim[base + k] << 16);
+                    BK[k] = P[k] / (uint32_t)a.rule.bucket;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < TINY_LOCS; k++) {
+                int rk = k;
+#pragma unroll
+                for (int j = k - 1; j >= 0; j--)
+                    if (BK[j] == BK[k] && ((sbits >> j) & 1u) == ((sbits >> k) & 1u)) rk = j;
+                repw |= (uint32_t)rk << (4 * k);
+            }
+        }
+        ReadState st{DINF, DINF, -1, -1, -1};
+        // a distance d <= limit at location k
+        auto record = [&](int k, int d) {
+            const int rk = (int)((repw >> (4 * k)) & 15u);
+            uint32_t pk = 0;
+            uint64_t bv = 0;
+#pragma unroll
+            for (int j = 0; j < TINY_LOCS; j++) {
+                if (j == k) pk = P[j];
+                if (j == rk) bv = BM[j];
+            }
+            const uint64_t nv0 = ((uint64_t)d << 32) | pk;
+            const uint64_t nv = nv0 < bv ? nv0 : bv;
+#pragma unroll
+            for (int j = 0; j < TINY_LOCS; j++)
+                if (j == rk) BM[j] = nv;
+            state_update(st, rk, (int)(nv >> 32), (int64_t)(nv & 0xFFFFFFFFull), (int)((sbits >> k) & 1u));
+        };
+        const int round0 = L / a.rule.s;
+        int t = 0, call = -1, need_k = -1;
+        int req_kind = 0, req_lim = 0;   // 0: location need_k at req_lim; 1: undecided at Kfull; 2: remaining at req_lim
+        bool looked = false, all_over = true, ended = false, unresolved = false;
+        uint32_t prefix = 0, scored = 0;
+        for (int i = 0; i < NS; i++) {
+            const int status = a.pr[r * NS + i].status;
+            if (status == ST_NONE) { ended = true; break; }
+            if (status == ST_N) continue;
+            looked = true;
+            if (status == ST_OVER) continue;
+            all_over = false;
+            prefix |= 1u << i;
+            if (i < round0) t++;
+            // the unscored location with the most seeds hitting; ties to the lower index
+            int kb = -1, bv = 0;
+            uint32_t dvb = 0;
+#pragma unroll
+            for (int k = 0; k < TINY_LOCS; k++) {
+                const int v = (k < C && !((scored >> k) & 1u)) ? __builtin_popcount(M[k] & prefix) : 0;
+                if (v > bv) { bv = v; kb = k; dvb = DV[k]; }
+            }
+            if (kb >= 0) {
+                const int lim = d_limit(st, dmax, c);
+                const int res = ed_answer((int)(dvb & 0xFFFFu), (int)(int16_t)(dvb >> 16), lim);
+                if (res == -2) {
+                    unresolved = true;
+                    need_k = kb;
+                    req_kind = all_undecided ? 1 : 0;
+                    req_lim = lim;
+                    break;
+                }
+                scored |= 1u << kb;
+                if (res >= 0) record(kb, res);
+            }
+            if (st.d_best < c && st.d_second < st.d_best + c) {
+                call = SNAP_MULTIPLE;
+                ended = true;
+                break;
+            }
+            if (st.d_best < DINF && t >= st.d_best + c) {
+                // score every remaining location: vote count descending, then index
+                for (int lev = __builtin_popcount(prefix); lev >= 1 && !unresolved; lev--) {
+#pragma unroll
+                    for (int k = 0; k < TINY_LOCS; k++) {
+                        if (!unresolved && k < C && !((scored >> k) & 1u) && __builtin_popcount(M[k] & prefix) == lev) {
+                            const int lim = d_limit(st, dmax, c);
+                            const int res = ed_answer((int)(DV[k] & 0xFFFFu), (int)(int16_t)(DV[k] >> 16), lim);
+                            if (res == -2) {
+                                unresolved = true;
+                                need_k = k;
+                                req_kind = 2;
+                                req_lim = all_undecided ? Kfull : lim;
+                            } else if (res >= 0) {
+                                record(k, res);
+                            }
+                        }
+                    }
+                }
+                ended = true;
+                break;
+            }
+        }
+        // all slots of this pass used and the read still has seeds to try
+        if (!ended && !unresolved && NS < seeds_for_length(a.rule, L) && seed_offset(a.sh, a.rule.s, L, NS) >= 0)
+            unresolved = true;
+        if (unresolved) {
+            if (need_k >= 0) {
+                // the locations asked for (see k_replay), listed at the read's first slot
+                const int code = req_kind == 1 ? Kfull : (lane_class ? req_lim : (REQ_WAVE | req_lim));
+                const int lr = req_kind == 1 ? Kfull : req_lim;
+                uint32_t n = 0;
+#pragma unroll
+                for (int k = 0; k < TINY_LOCS; k++) {
+                    const int dc = (int)(DV[k] & 0xFFFFu), vl = (int)(int16_t)(DV[k] >> 16);
+                    bool want;
+                    if (req_kind == 0) want = k == need_k;
+                    else if (req_kind == 1) want = dc > vl && vl < lr;
+                    else want = !((scored >> k) & 1u) && (M[k] & prefix) && dc > vl && vl < lr;
+                    if (k < C && want) {
+                        a.rq[base + k] = (int16_t)code;
+                        a.req_area[base + n] = (uint32_t)(base + k);
+                        n++;
+                    }
+                }
+                a.reqcount[r] = n | ((!lane_class) ? REQ_WAVE_READ : 0u);
+            }
+            a.rflag[r] = need_k < 0 ? RF_PENDING : RF_REPLAY;
+            continue;
+        }
+        if (call < 0) {
+            if (st.d_best <= dmax && st.d_second >= st.d_best + c) call = SNAP_SINGLE;
+            else if (st.d_best <= dmax || (looked && all_over)) call = SNAP_MULTIPLE;
+            else call = SNAP_NOT_FOUND;
+        }
+        const bool has = st.d_best < DINF;
+        a.rflag[r] = RF_DONE;
+        a.pos[g] = has ? st.best_p : -1;
+        a.strand[g] = (int8_t)(has ? st.best_s : -1);
+        a.dist[g] = has ? st.d_best : -1;
+        a.second[g] = st.d_second < DINF ? st.d_second : -1;
+        a.call[g] = (int8_t)call;
+    }
+}
+
 // Chunk read indices -> global read ids (the list a later pass works on).
 __global__ void k_map_gid(const uint32_t *in, const int64_t *n_ptr, Pass ps, uint32_t *out) {
     const int64_t n = *n_ptr;
@@ -1603,27 +1775,28 @@ struct FirstSeedsPred {
     __host__ __device__ bool operator()(uint32_t k) const { return (int64_t)k < *ncand && (mask[k] & bits) != 0; }
 };
 
-// Entries of a read list (or reads [0, items) when it is null) with more than 64 locations.
+// Entries r of a read list (or reads [0, items) when it is null) with lo < count[r] <= hi.
 struct ListAt {
     const uint32_t *list;
     __host__ __device__ uint32_t operator()(uint32_t i) const { return list ? list[i] : i; }
 };
-struct HeavyPred {
+struct CountRangePred {
     const uint32_t *count;
-    __host__ __device__ bool operator()(uint32_t r) const { return count[r] > 64; }
+    uint32_t lo, hi;
+    __host__ __device__ bool operator()(uint32_t r) const { return count[r] > lo && count[r] <= hi; }
 };
 
-hipError_t select_heavy(void *tmp, size_t &tmp_bytes, int64_t items, const uint32_t *list, const uint32_t *count,
-                        uint32_t *out, int64_t *nsel, hipStream_t st) {
+hipError_t select_count_range(void *tmp, size_t &tmp_bytes, int64_t items, const uint32_t *list, const uint32_t *count,
+                              uint32_t lo, uint32_t hi, uint32_t *out, int64_t *nsel, hipStream_t st) {
     hipcub::CountingInputIterator<uint32_t> ci(0);
     hipcub::TransformInputIterator<uint32_t, ListAt, hipcub::CountingInputIterator<uint32_t>> it(ci, ListAt{list});
-    return hipcub::DeviceSelect::If(tmp, tmp_bytes, it, out, nsel, (int)items, HeavyPred{count}, st);
+    return hipcub::DeviceSelect::If(tmp, tmp_bytes, it, out, nsel, (int)items, CountRangePred{count, lo, hi}, st);
 }
 
 size_t select_tmp_bytes(int64_t items) {
     size_t a = 0, b = 0, c = 0;
     (void)select_idx(nullptr, a, items, FlagPred{nullptr, 0}, nullptr, nullptr, 0);
-    (void)select_heavy(nullptr, b, items, nullptr, nullptr, nullptr, nullptr, 0);
+    (void)select_count_range(nullptr, b, items, nullptr, nullptr, 0, 0, nullptr, nullptr, 0);
     (void)select_idx(nullptr, c, items, FirstSeedsPred{nullptr, nullptr, 0}, nullptr, nullptr, 0);
     size_t d = 0;
     (void)select_idx(nullptr, d, items, HitRangePred{nullptr, 0, 0}, nullptr, nullptr, 0);
@@ -1671,8 +1844,8 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     l.off_ccount = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
     l.off_coff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
     l.off_scan = o; o = align256(o + std::max(scan_tmp_bytes(R + 1), scan_tmp_bytes(n + 1)));
-    // read flags; replay and next-pass lists, request counts; request offsets
-    l.off_req = o; o = align256(o + (size_t)R); o = align256(o + 3 * sizeof(uint32_t) * (size_t)R);
+    // read flags; replay and next-pass lists, request counts, light-replay list; request offsets
+    l.off_req = o; o = align256(o + (size_t)R); o = align256(o + 4 * sizeof(uint32_t) * (size_t)R);
     o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
     const int64_t minslots = (int64_t)NS * hmax;
     if (pool_slots < minslots) pool_slots = minslots;
@@ -1856,7 +2029,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     uint32_t *pend_local = replay_list + R;
     uint32_t *reqcount = pend_local + R;
     uint32_t *heavy_list = pend_local;   // free while a pass replays (the next-pass list is made after)
-    int64_t *req_off = (int64_t *)(ws + align256(l.off_req + (size_t)R) + align256(3 * sizeof(uint32_t) * (size_t)R));
+    uint32_t *light_list = reqcount + R;
+    int64_t *req_off = (int64_t *)(ws + align256(l.off_req + (size_t)R) + align256(4 * sizeof(uint32_t) * (size_t)R));
     const int64_t PS = l.pool_slots;
     char *pool = ws + l.off_pool;
     auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
@@ -2044,11 +2218,20 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                           rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax, pos, strand,
                           dist, second, call};
             const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
-            // reads with more than 64 locations replay from their own list
+            // reads with up to TINY_LOCS locations replay a lane each; the others, a wave
+            // each, from their own lists (up to 64 locations in registers, more in LDS)
             auto replay = [&](const ReplayArgs &x, unsigned blocks, int64_t items) {
-                timed("replay", st, [&] { hipLaunchKernelGGL(k_replay<true>, dim3(blocks), dim3(256), 0, st, x); });
+                const unsigned tb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, (int64_t)cus * 32));
+                timed("replay_tiny", st, [&] { hipLaunchKernelGGL(k_replay_tiny, dim3(tb), dim3(256), 0, st, x); });
+                if (maxH > TINY_LOCS) {
+                    (void)select_count_range(sel_tmp, sel_tb, items, x.rlist, ccount, TINY_LOCS, 64u, light_list, sel_n + 8, st);
+                    ReplayArgs l = x;
+                    l.rlist = light_list;
+                    l.rlist_n = sel_n + 8;
+                    timed("replay", st, [&] { hipLaunchKernelGGL(k_replay<true>, dim3(blocks), dim3(256), 0, st, l); });
+                }
                 if (maxH > 64) {
-                    (void)select_heavy(sel_tmp, sel_tb, items, x.rlist, ccount, heavy_list, sel_n + 4, st);
+                    (void)select_count_range(sel_tmp, sel_tb, items, x.rlist, ccount, 64u, 0xFFFFFFFFu, heavy_list, sel_n + 4, st);
                     ReplayArgs h = x;
                     h.rlist = heavy_list;
                     h.rlist_n = sel_n + 4;
