@@ -1543,7 +1543,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
 // Reads with at most TINY_LOCS locations (most reads: a unique region gives one or
 // two): one lane per read, Algorithm 1's control flow run sequentially over
 // registers (the same decisions as the wave paths, in the same order).
-constexpr int TINY_LOCS = 4;
+constexpr int TINY_LOCS = 8;
 
 __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
     const int64_t nlist = a.rlist ? *a.rlist_n : a.ps.nr;
