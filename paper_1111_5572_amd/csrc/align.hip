@@ -460,7 +460,10 @@ __global__ __launch_bounds__(256) void k_dedupe_light(DedupeArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r = wave; r < a.nr; r += nwaves) {
+    const int64_t n = a.rlist ? *a.rlist_n : a.nr;
+    for (int64_t ri = wave; ri < n; ri += nwaves) {
+        const int64_t r = a.rlist ? (int64_t)a.rlist[ri] : ri;
+        if (r >= a.nr) continue;
         const uint32_t H = a.hits[r];
         if (H > 64) continue;
         const int64_t base = a.hoff[r];
@@ -495,6 +498,46 @@ __global__ __launch_bounds__(256) void k_dedupe_light(DedupeArgs a) {
         }
         if ((uint32_t)lane < H) a.slot_read[base + lane] = (uint32_t)r;
         if (lane == 0) a.count[r] = (uint32_t)__popcll(fb);
+    }
+}
+
+// Reads with at most 8 hits (most reads): one lane per read, a 19-comparator sorting
+// network over registers, then the same merge of equal locations.
+__global__ __launch_bounds__(256) void k_dedupe_tiny(DedupeArgs a) {
+    constexpr int N = 8;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.nr; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t H = a.hits[r];
+        if (H > (uint32_t)N) continue;
+        const int64_t base = a.hoff[r];
+        uint64_t v[N];
+#pragma unroll
+        for (int k = 0; k < N; k++) v[k] = (uint32_t)k < H ? a.hk[base + k] : HIT_NONE;
+        constexpr int net[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                                    {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+        for (int q = 0; q < 19; q++) {
+            const uint64_t x = v[net[q][0]], y = v[net[q][1]];
+            v[net[q][0]] = x < y ? x : y;
+            v[net[q][1]] = x < y ? y : x;
+        }
+        uint32_t n = 0, acc = 0;
+        uint64_t cur = 0;
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            if (v[k] == HIT_NONE) continue;
+            const uint64_t loc = v[k] >> 5;
+            if (n > 0 && loc == cur) {
+                acc |= 1u << (v[k] & 31);
+            } else {
+                if (n > 0) { a.key[base + n - 1] = cur; a.mask[base + n - 1] = acc; }
+                cur = loc;
+                acc = 1u << (v[k] & 31);
+                n++;
+            }
+        }
+        if (n > 0) { a.key[base + n - 1] = cur; a.mask[base + n - 1] = acc; }
+        for (uint32_t k = 0; k < H; k++) a.slot_read[base + k] = (uint32_t)r;
+        a.count[r] = n;
     }
 }
 
@@ -2099,9 +2142,11 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             HIP_OK(hipMemcpyAsync(misc + 1, hoff + nr, 8, hipMemcpyDeviceToDevice, st));
             HIP_OK(select_idx(sel_tmp, sel_tb, nr, HitRangePred{hits, 64u, 512u}, replay_list, sel_n + 6, st));
             HIP_OK(select_idx(sel_tmp, sel_tb, nr, HitRangePred{hits, 512u, 0xFFFFFFFFu}, pend_local, sel_n + 7, st));
-            int64_t sc[2], ntier[2];
+            HIP_OK(select_idx(sel_tmp, sel_tb, nr, HitRangePred{hits, 8u, 64u}, light_list, sel_n + 9, st));
+            int64_t sc[2], ntier[3];
             HIP_OK(hipMemcpyAsync(sc, misc, 16, hipMemcpyDeviceToHost, st));
             HIP_OK(hipMemcpyAsync(ntier, sel_n + 6, 16, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipMemcpyAsync(ntier + 2, sel_n + 9, 8, hipMemcpyDeviceToHost, st));
             HIP_OK(hipStreamSynchronize(st));
             const uint32_t maxH = (uint32_t)(sc[0] & 0x7FFFFFFF);
             int64_t total = sc[1];
@@ -2124,8 +2169,16 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             }
             DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, slot_read, nullptr, nullptr};
             {
-                const unsigned lb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
-                timed("dedupe_light", st, [&] { hipLaunchKernelGGL(k_dedupe_light, dim3(lb), dim3(256), 0, st, da); });
+                // up to 8 hits: a lane per read; up to 64: a wave per read, from its own list
+                const unsigned tb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + 255) / 256, (int64_t)cus * 32));
+                timed("dedupe_tiny", st, [&] { hipLaunchKernelGGL(k_dedupe_tiny, dim3(tb), dim3(256), 0, st, da); });
+                if (ntier[2] > 0) {
+                    DedupeArgs dl = da;
+                    dl.rlist = light_list;
+                    dl.rlist_n = sel_n + 9;
+                    const unsigned lb = (unsigned)std::min<int64_t>((ntier[2] + 3) / 4, 8192);
+                    timed("dedupe_light", st, [&] { hipLaunchKernelGGL(k_dedupe_light, dim3(lb), dim3(256), 0, st, dl); });
+                }
             }
             // reads beyond 64 hits sort from their own lists (a chunk that shrank to fit the
             // pool keeps the lists of the whole chunk: the entries past nr are skipped)
