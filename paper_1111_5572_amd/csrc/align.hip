@@ -692,7 +692,7 @@ struct Stage {
 // while read and text bases are equal (N equals nothing), 16 bases per step.
 // HAS_N false: neither the read nor the window holds an N, so the N masks are skipped.
 template <bool HAS_N>
-__device__ inline int slide(const Stage &st, int i, int d, int L, int Tn) {
+__device__ __forceinline__ int slide(const Stage &st, int i, int d, int L, int Tn) {
     for (;;) {
         const int j = i + d;
         const int rem = min(L - i, Tn - j);
@@ -737,12 +737,49 @@ __device__ inline int lv_lane(const Stage &st, int L, int Tn, int K, uint32_t &n
     return K + 1;
 }
 
+// The same with the furthest rows in registers, for limits up to KM (every diagonal
+// index is a compile-time constant once the rounds are unrolled).
+template <int KM, bool HAS_N>
+__device__ __forceinline__ int lv_lane_reg(const Stage &st, int L, int Tn, int K, uint32_t &nsteps) {
+    constexpr int NEG = -30000;
+    const int i0 = slide<HAS_N>(st, 0, 0, L, Tn);
+    if (i0 >= L) return 0;
+    int fr[2 * KM + 3];
+#pragma unroll
+    for (int t = 0; t < 2 * KM + 3; t++) fr[t] = NEG;
+    fr[KM + 1] = i0;
+    int D = K + 1;
+#pragma unroll
+    for (int e = 1; e <= KM; e++) {
+        if (e <= K && D > K) {
+            int left = NEG;   // previous round's value on diagonal d - 1
+#pragma unroll
+            for (int d = -e; d <= e; d++) {
+                const int idx = d + KM + 1;
+                const int od = fr[idx], orr = fr[idx + 1];
+                int i = max(left, max(od, orr) + 1);
+                left = od;
+                i = min(i, min(L, Tn - d));
+                if (i >= max(0, -d) && D > K) {
+                    nsteps++;
+                    i = slide<HAS_N>(st, i, d, L, Tn);
+                    if (i >= L) D = e;
+                } else {
+                    i = NEG;
+                }
+                fr[idx] = i;
+            }
+        }
+    }
+    return D;
+}
+
 // Bounded edit distance (Section 3.2): D = min over j of Lev(read', text[0, j)),
 // start anchored at p, end free, read' the read or its reverse complement.
 // Furthest-reaching rows per diagonal, e = 0, 1, ..., limit; returns D if D <= K,
 // else K + 1.
 template <int KMAX>
-__device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm) {
+__device__ __forceinline__ void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm) {
     const int lane = threadIdx.x & 63;
     Stage st;
     st.lane = lane;
@@ -804,7 +841,11 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
     st.strand = strand;
 
     uint32_t nsteps = 1;
-    const int D = anyn ? lv_lane<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane<KMAX, false>(st, L, Tn, K, nsteps);
+    int D;
+    if constexpr (KMAX <= 7)
+        D = anyn ? lv_lane_reg<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane_reg<KMAX, false>(st, L, Tn, K, nsteps);
+    else
+        D = anyn ? lv_lane<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane<KMAX, false>(st, L, Tn, K, nsteps);
     a.dcap[k] = (uint16_t)D;
     a.vlim[k] = (int16_t)K;
     if (a.steps) a.steps[k] = (a.rq ? a.steps[k] : 0u) + nsteps;
@@ -812,7 +853,7 @@ __device__ inline void verify_lane(const VerifyArgs &a, int64_t k, uint32_t *sm)
 
 
 template <int KMAX>
-__device__ inline void verify_lanes(const VerifyArgs &a, uint32_t *sm) {
+__device__ __forceinline__ void verify_lanes(const VerifyArgs &a, uint32_t *sm) {
     const int lane = threadIdx.x;
     const int64_t n = a.list ? *a.nlist_ptr : *a.ncand_ptr;
     for (int64_t idx = (int64_t)blockIdx.x * 64 + lane; idx < n; idx += (int64_t)gridDim.x * 64)
@@ -2119,7 +2160,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int RW = (std::max(lane_L, 1) + 15) / 16 + 1;
         const int TW = (std::max(lane_L, 1) + lane_K + 15) / 16 + 1;
         const int kmax_t = lane_K <= 7 ? 7 : (lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63));
-        const size_t lds = (size_t)64 * 4 * (RW + TW) + (size_t)64 * 2 * (2 * kmax_t + 3);
+        // furthest rows in LDS only above limit 7 (registers below)
+        const size_t lds = (size_t)64 * 4 * (RW + TW) + (kmax_t > 7 ? (size_t)64 * 2 * (2 * kmax_t + 3) : 0);
         // wave-per-location tile: any read, any limit (requests go up to the full limit)
         const int Kw = Kmax;
         const int RWL = (std::max(maxL, 1) + 15) / 16 + 1;
@@ -2311,7 +2353,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     const int kfull = std::min(Kmax, LANE_KMAX);
                     const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
                     const int kmf = kfull <= 7 ? 7 : (kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63));
-                    const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (size_t)64 * 2 * (2 * kmf + 3);
+                    const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 7 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
                     VerifyArgs vq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
                                   coff + nr, rule, RW, TWf, dcap, vlim, steps, long_list, req_off + nrep, rq};
                     // as many waves as fit the device (the count is on the device)
