@@ -172,6 +172,9 @@ typedef struct {
     int32_t verify_seeds;   /* snap_align, reads in the lane tile: the first verification covers only
                                locations hit by one of the first verify_seeds seed slots, the others
                                are verified when a replay asks (0 = all locations) */
+    int32_t chunk_reads;    /* reads per chunk pass (0 = 2^20); a batch of several chunks is worked
+                               by two host threads with a stream each when the workspace holds two
+                               chunk parts */
 } snap_tuning;
 
 int snap_set_tuning(const snap_tuning *t);
@@ -292,6 +295,7 @@ typedef struct {
     int64_t lv_steps;     /* diagonal extensions run by the verify kernel */
     int64_t second_pass_reads; /* reads a first pass left to a later pass */
     int64_t requests;     /* replays of reads after the verification they asked for */
+    int64_t workers;      /* most chunk workers (host thread + stream) one call used */
 } snap_counters;
 
 int snap_profile_counters(snap_counters *out);

@@ -25,9 +25,11 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/snapgpu.h"
@@ -1891,9 +1893,11 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     // batch part
-    size_t off_roff, off_rcode, off_rmask, off_misc, off_pending;
-    // chunk part
-    size_t off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan, off_sel, off_req, off_pool;
+    size_t off_roff, off_rcode, off_rmask, off_pending;
+    // chunk part, one per worker, offsets from the start of a worker's part
+    size_t off_misc, off_probe, off_hits, off_hoff, off_ccount, off_coff, off_scan, off_sel, off_req, off_pool;
+    size_t chunk_base, chunk_bytes;
+    int workers;
     int64_t R;             // reads per chunk
     int64_t pool_slots;    // hit / location slots per chunk
     size_t total;
@@ -1912,16 +1916,19 @@ size_t scan_tmp_bytes(int64_t items) {
     return b;
 }
 
-Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t pool_slots) {
+Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t pool_slots, int workers = 1) {
     Layout l{};
     size_t o = 0;
     l.off_roff = o; o = align256(o + sizeof(int64_t) * (size_t)(n + 1));
     const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
     l.off_rcode = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)nblk);
     l.off_rmask = o; o = align256(o + sizeof(uint32_t) * (size_t)nblk);
-    l.off_misc = o; o = align256(o + 256);
     l.off_pending = o; o = align256(o + 2 * sizeof(uint32_t) * (size_t)n);
+    l.chunk_base = o;
     l.R = R;
+    l.workers = workers;
+    o = 0;
+    l.off_misc = o; o = align256(o + 256);
     l.off_probe = o; o = align256(o + sizeof(ProbeRec) * (size_t)R * NS);
     l.off_hits = o; o = align256(o + sizeof(uint32_t) * (size_t)R);
     l.off_hoff = o; o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
@@ -1936,7 +1943,8 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     l.pool_slots = pool_slots;
     l.off_sel = o; o = align256(o + select_tmp_bytes(std::max<int64_t>(R, pool_slots) + 1));
     l.off_pool = o; o = align256(o + POOL_SLOT_BYTES * (size_t)pool_slots + POOL_ARRAYS * 256);
-    l.total = o;
+    l.chunk_bytes = o;
+    l.total = l.chunk_base + (size_t)workers * l.chunk_bytes;
     return l;
 }
 
@@ -1980,10 +1988,48 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {5, 6, 6, 0, 1, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
+snap_tuning g_tune = {5, 6, 6, 0, 1, 0, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
                                         // exact-request rounds, first-verification seeds
 
 constexpr int KCAP_NONE = 1 << 20;
+
+// Streams (default priority, non-blocking) kept per device for the second worker of
+// snap_align calls; a call leases one with an event and returns both when it ends.
+std::mutex g_stream_mu;
+std::vector<std::pair<int, std::pair<hipStream_t, hipEvent_t>>> g_stream_free;
+
+struct StreamLease {
+    int dev = -1;
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    explicit StreamLease(int device) : dev(device) {
+        if (dev < 0) return;
+        {
+            std::lock_guard<std::mutex> g(g_stream_mu);
+            for (size_t i = 0; i < g_stream_free.size(); i++) {
+                if (g_stream_free[i].first == dev) {
+                    s = g_stream_free[i].second.first;
+                    ev = g_stream_free[i].second.second;
+                    g_stream_free.erase(g_stream_free.begin() + (long)i);
+                    return;
+                }
+            }
+        }
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { s = nullptr; return; }
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(s);
+            s = nullptr;
+        }
+    }
+    ~StreamLease() {
+        if (dev < 0 || !s) return;
+        (void)hipStreamSynchronize(s);
+        std::lock_guard<std::mutex> g(g_stream_mu);
+        g_stream_free.push_back({dev, {s, ev}});
+    }
+    StreamLease(const StreamLease &) = delete;
+    StreamLease &operator=(const StreamLease &) = delete;
+};
 
 }  // namespace
 
@@ -1996,7 +2042,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0 || t->chunk_reads < 0) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -2037,7 +2083,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
-    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0) return SNAP_EINVAL;
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0 || tune.chunk_reads < 0) return SNAP_EINVAL;
     const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
     const int exact_rounds = tune.exact_rounds;
     const int verify_seeds = tune.verify_seeds;
@@ -2050,7 +2096,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
 
     // read offsets, total bases and longest read (one wait for two scalars)
     Layout l0 = make_layout(n_reads, 0, 1, 1, 1, 0);
-    if (ws_bytes < l0.off_probe + 4096) return SNAP_ENOMEM;
+    if (ws_bytes < l0.chunk_base + 4096) return SNAP_ENOMEM;
     char *ws = (char *)workspace;
     int64_t *roff = (int64_t *)(ws + l0.off_roff);
     // until the layout is known (it needs the total), two scalars live at the tail
@@ -2077,7 +2123,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     if (Kmax > VERIFY_KMAX || maxL > VERIFY_LMAX) return SNAP_EINVAL;
 
     // chunk size and pool from the workspace
-    int64_t R = std::min<int64_t>(n_reads, CHUNK_READS);
+    int64_t R = std::min<int64_t>(n_reads, tune.chunk_reads > 0 ? tune.chunk_reads : CHUNK_READS);
     Layout l = make_layout(n_reads, B, NS, rule.hmax, R, 0);
     while (l.total > ws_bytes && R > 1) {
         R = std::max<int64_t>(1, R / 2);
@@ -2092,49 +2138,93 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots - over);
         }
     }
+    // two workers (a host thread and a stream each, and a chunk part of the workspace
+    // each) when the batch spans several chunks and the workspace holds two parts
+    // with room for the hits of a typical chunk: one worker's host waits and small
+    // kernels then overlap the other's work
+    int workers = 1;
+    if (n_reads > R) {
+        Layout l2 = make_layout(n_reads, B, NS, rule.hmax, R, 0, 2);
+        if (l2.total <= ws_bytes) {
+            const int64_t extra = (int64_t)((ws_bytes - l2.total) / (2 * POOL_SLOT_BYTES));
+            l2 = make_layout(n_reads, B, NS, rule.hmax, R, l2.pool_slots + extra, 2);
+            while (l2.total > ws_bytes) {
+                const int64_t over = (int64_t)((l2.total - ws_bytes) / (2 * POOL_SLOT_BYTES)) + 64;
+                l2 = make_layout(n_reads, B, NS, rule.hmax, R, l2.pool_slots - over, 2);
+            }
+            if (l2.pool_slots >= 16 * R) {
+                l = l2;
+                workers = 2;
+            }
+        }
+    }
     uint32_t *rcode = (uint32_t *)(ws + l.off_rcode);
     uint32_t *rmask = (uint32_t *)(ws + l.off_rmask);
-    int64_t *misc = (int64_t *)(ws + l.off_misc);
-    unsigned long long *steps_sum = (unsigned long long *)(misc + 6);
-    int64_t *sel_n = misc + 20;   // selected counts: [2] reads to replay, [3] reads for the next pass
     uint32_t *pending_out = nullptr;
     int64_t pend_count = 0;
+    std::mutex pend_mu;
     uint32_t *pending = (uint32_t *)(ws + l.off_pending);
-    ProbeRec *probe = (ProbeRec *)(ws + l.off_probe);
-    uint32_t *hits = (uint32_t *)(ws + l.off_hits);
-    int64_t *hoff = (int64_t *)(ws + l.off_hoff);
-    uint32_t *ccount = (uint32_t *)(ws + l.off_ccount);
-    int64_t *coff = (int64_t *)(ws + l.off_coff);
-    void *scan_tmp = ws + l.off_scan;
-    void *sel_tmp = ws + l.off_sel;
-    size_t sel_tb = select_tmp_bytes(std::max<int64_t>(R, l.pool_slots) + 1);
-    uint8_t *rflag = (uint8_t *)(ws + l.off_req);
-    uint32_t *replay_list = (uint32_t *)(ws + align256(l.off_req + (size_t)R));
-    uint32_t *pend_local = replay_list + R;
-    uint32_t *reqcount = pend_local + R;
-    uint32_t *heavy_list = pend_local;   // free while a pass replays (the next-pass list is made after)
-    uint32_t *light_list = reqcount + R;
-    int64_t *req_off = (int64_t *)(ws + align256(l.off_req + (size_t)R) + align256(4 * sizeof(uint32_t) * (size_t)R));
+    const size_t sel_tb_all = select_tmp_bytes(std::max<int64_t>(R, l.pool_slots) + 1);
     const int64_t PS = l.pool_slots;
-    char *pool = ws + l.off_pool;
-    auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
-    uint64_t *hk = (uint64_t *)carve(8 * (size_t)PS);
-    uint64_t *key_res = (uint64_t *)carve(8 * (size_t)PS);
-    uint32_t *mask_res = (uint32_t *)carve(4 * (size_t)PS);
-    uint32_t *slot_read = (uint32_t *)carve(4 * (size_t)PS);
-    uint64_t *key_c = (uint64_t *)carve(8 * (size_t)PS);
-    uint32_t *mask_c = (uint32_t *)carve(4 * (size_t)PS);
-    uint32_t *cread = (uint32_t *)carve(4 * (size_t)PS);
-    uint64_t *bmin = (uint64_t *)carve(8 * (size_t)PS);
-    uint16_t *dcap = (uint16_t *)carve(2 * (size_t)PS);
-    int16_t *vlim = (int16_t *)carve(2 * (size_t)PS);
-    uint8_t *scored = (uint8_t *)carve((size_t)PS);
-    uint32_t *short_list = (uint32_t *)carve(4 * (size_t)PS);
-    uint32_t *long_list = (uint32_t *)carve(4 * (size_t)PS);
-    int16_t *rq = (int16_t *)carve(2 * (size_t)PS);
-    unsigned long long *route_cnt = (unsigned long long *)(misc + 8);   // two counters
-    unsigned long long *steal_next = (unsigned long long *)(misc + 10);  // two cursors
-    const int64_t *zero_count = (const int64_t *)(misc + 14);
+    struct Worker {
+        hipStream_t st;
+        int64_t *misc;
+        ProbeRec *probe;
+        uint32_t *hits;
+        int64_t *hoff;
+        uint32_t *ccount;
+        int64_t *coff;
+        void *scan_tmp, *sel_tmp;
+        uint8_t *rflag;
+        uint32_t *replay_list, *pend_local, *reqcount, *light_list;
+        int64_t *req_off;
+        uint64_t *hk, *key_res;
+        uint32_t *mask_res, *slot_read;
+        uint64_t *key_c;
+        uint32_t *mask_c, *cread;
+        uint64_t *bmin;
+        uint16_t *dcap;
+        int16_t *vlim;
+        uint8_t *scored;
+        uint32_t *short_list, *long_list;
+        int16_t *rq;
+    };
+    Worker wk[2];
+    for (int w = 0; w < workers; w++) {
+        char *cb = ws + l.chunk_base + (size_t)w * l.chunk_bytes;
+        Worker &W = wk[w];
+        W.misc = (int64_t *)(cb + l.off_misc);
+        W.probe = (ProbeRec *)(cb + l.off_probe);
+        W.hits = (uint32_t *)(cb + l.off_hits);
+        W.hoff = (int64_t *)(cb + l.off_hoff);
+        W.ccount = (uint32_t *)(cb + l.off_ccount);
+        W.coff = (int64_t *)(cb + l.off_coff);
+        W.scan_tmp = cb + l.off_scan;
+        W.sel_tmp = cb + l.off_sel;
+        W.rflag = (uint8_t *)(cb + l.off_req);
+        W.replay_list = (uint32_t *)(cb + align256(l.off_req + (size_t)R));
+        W.pend_local = W.replay_list + R;
+        W.reqcount = W.pend_local + R;
+        W.light_list = W.reqcount + R;
+        W.req_off = (int64_t *)(cb + align256(l.off_req + (size_t)R) + align256(4 * sizeof(uint32_t) * (size_t)R));
+        char *pool = cb + l.off_pool;
+        auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
+        W.hk = (uint64_t *)carve(8 * (size_t)PS);
+        W.key_res = (uint64_t *)carve(8 * (size_t)PS);
+        W.mask_res = (uint32_t *)carve(4 * (size_t)PS);
+        W.slot_read = (uint32_t *)carve(4 * (size_t)PS);
+        W.key_c = (uint64_t *)carve(8 * (size_t)PS);
+        W.mask_c = (uint32_t *)carve(4 * (size_t)PS);
+        W.cread = (uint32_t *)carve(4 * (size_t)PS);
+        W.bmin = (uint64_t *)carve(8 * (size_t)PS);
+        W.dcap = (uint16_t *)carve(2 * (size_t)PS);
+        W.vlim = (int16_t *)carve(2 * (size_t)PS);
+        W.scored = (uint8_t *)carve((size_t)PS);
+        W.short_list = (uint32_t *)carve(4 * (size_t)PS);
+        W.long_list = (uint32_t *)carve(4 * (size_t)PS);
+        W.rq = (int16_t *)carve(2 * (size_t)PS);
+        if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
+    }
     int64_t steal_waves = 2048;
     int cus = 256;
     {
@@ -2142,14 +2232,27 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0) cus = c;
         steal_waves = (int64_t)cus * 8;
     }
-    if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
-    // per-location step counts reuse the hit array, dead once locations are compacted
-    uint32_t *steps = g_prof_on ? (uint32_t *)hk : nullptr;
+    // the second worker's stream, from a pool of the device's streams; it starts once
+    // the read stream is packed on the caller's stream
+    wk[0].st = st;
+    if (g_prof_on) {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        g_ctr.workers = std::max<int64_t>(g_ctr.workers, workers);
+    }
+    StreamLease lease(workers > 1 ? dev : -1);
+    if (workers > 1) {
+        if (!lease.s) return SNAP_EDEVICE;
+        wk[1].st = lease.s;
+    }
 
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)misc, 64, 0u);
+    for (int w = 0; w < workers; w++) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)wk[w].misc, 64, 0u);
     {
         const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
         timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk); });
+    }
+    if (workers > 1) {
+        HIP_OK(hipEventRecord(lease.ev, st));
+        HIP_OK(hipStreamWaitEvent(wk[1].st, lease.ev, 0));
     }
     // one pass over a list of reads (all reads, or the ones an earlier pass left)
     auto run_pass = [&](const uint32_t *ridx, int64_t list_len, int NSp, int Kcap, int final_pass) -> int {
@@ -2168,8 +2271,47 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int TWL = (std::max(maxL, 1) + Kw + 15) / 16 + 1;
         const size_t lds_wave = (size_t)4 * (2 * RWL + 2 * TWL) + (size_t)8 * (2 * Kw + 3);
         if (lds > (size_t)lds_max || (!all_lane && lds_wave > (size_t)lds_max)) return SNAP_EINVAL;
-        for (int64_t r0 = 0; r0 < list_len;) {
-            int64_t nr = std::min<int64_t>(R, list_len - r0);
+        // workers take ranges of R reads of the list in turn; a range whose hits do not
+        // fit the pool is done in several chunks
+        std::atomic<int64_t> next_range{0};
+        auto work = [&](Worker &W) -> int {
+        hipStream_t st = W.st;
+        int64_t *misc = W.misc;
+        ProbeRec *probe = W.probe;
+        uint32_t *hits = W.hits;
+        int64_t *hoff = W.hoff;
+        uint32_t *ccount = W.ccount;
+        int64_t *coff = W.coff;
+        void *scan_tmp = W.scan_tmp, *sel_tmp = W.sel_tmp;
+        size_t sel_tb = sel_tb_all;
+        uint8_t *rflag = W.rflag;
+        uint32_t *replay_list = W.replay_list, *pend_local = W.pend_local, *reqcount = W.reqcount,
+                 *light_list = W.light_list;
+        uint32_t *heavy_list = pend_local;   // free while a chunk replays (the next-pass list is made after)
+        int64_t *req_off = W.req_off;
+        uint64_t *hk = W.hk, *key_res = W.key_res;
+        uint32_t *mask_res = W.mask_res, *slot_read = W.slot_read;
+        uint64_t *key_c = W.key_c;
+        uint32_t *mask_c = W.mask_c, *cread = W.cread;
+        uint64_t *bmin = W.bmin;
+        uint16_t *dcap = W.dcap;
+        int16_t *vlim = W.vlim;
+        uint8_t *scored = W.scored;
+        uint32_t *short_list = W.short_list, *long_list = W.long_list;
+        int16_t *rq = W.rq;
+        unsigned long long *steps_sum = (unsigned long long *)(misc + 6);
+        int64_t *sel_n = misc + 20;   // selected counts: [2] reads to replay, [3] reads for the next pass, ...
+        unsigned long long *route_cnt = (unsigned long long *)(misc + 8);   // two counters
+        unsigned long long *steal_next = (unsigned long long *)(misc + 10);  // two cursors
+        const int64_t *zero_count = (const int64_t *)(misc + 14);
+        // per-location step counts reuse the hit array, dead once locations are compacted
+        uint32_t *steps = g_prof_on ? (uint32_t *)hk : nullptr;
+        for (;;) {
+          const int64_t a0 = next_range.fetch_add(R);
+          if (a0 >= list_len) break;
+          const int64_t b0 = std::min<int64_t>(a0 + R, list_len);
+          for (int64_t r0 = a0; r0 < b0;) {
+            int64_t nr = std::min<int64_t>(R, b0 - r0);
             Pass ps{ridx, r0, nr, NSp, Kcap, final_pass};
             ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, ps, rule, sh, probe};
             const int64_t pthreads = nr * NSp * 8;
@@ -2389,14 +2531,21 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     g_ctr.requests += nrep;
                 }
             }
-            // reads that need more seeds go to the next pass
+            // reads that need more seeds go to the next pass (at a place of the shared
+            // list reserved once their number is known)
             if (!final_pass) {
                 HIP_OK(select_idx(sel_tmp, sel_tb, nr, FlagPred{rflag, RF_PENDING}, pend_local, sel_n + 3, st));
-                hipLaunchKernelGGL(k_map_gid, dim3(256), dim3(256), 0, st, pend_local, sel_n + 3, ps, pending_out + pend_count);
                 int64_t np = 0;
                 HIP_OK(hipMemcpyAsync(&np, sel_n + 3, 8, hipMemcpyDeviceToHost, st));
                 HIP_OK(hipStreamSynchronize(st));
-                pend_count += np;
+                int64_t at = 0;
+                {
+                    std::lock_guard<std::mutex> g(pend_mu);
+                    at = pend_count;
+                    pend_count += np;
+                }
+                if (np > 0)
+                    hipLaunchKernelGGL(k_map_gid, dim3(256), dim3(256), 0, st, pend_local, sel_n + 3, ps, pending_out + at);
             }
             HIP_OK(hipGetLastError());
             if (g_prof_on) {
@@ -2420,8 +2569,24 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 if (ridx) g_ctr.second_pass_reads += nr;
             }
             r0 += nr;
+          }
         }
+        HIP_OK(hipStreamSynchronize(st));
+        HIP_OK(hipGetLastError());
         return SNAP_OK;
+        };
+        if (workers == 1) return work(wk[0]);
+        int rc1 = SNAP_OK;
+        std::thread t1([&] {
+            if (hipSetDevice(dev) != hipSuccess) {
+                rc1 = SNAP_EDEVICE;
+                return;
+            }
+            rc1 = work(wk[1]);
+        });
+        const int rc0 = work(wk[0]);
+        t1.join();
+        return rc0 != SNAP_OK ? rc0 : rc1;
     };
 
     // stage 1 (when it is not complete): the first pass1_seeds seeds, locations

@@ -139,19 +139,21 @@ def test_small_workspace_many_passes(snapgpu, oracle_mod, synth_mod):
     assert nbad == 0, rep
 
 
-@pytest.mark.parametrize("seeds,limit,limit2,rounds,vseeds", [
-    (0, 0, 0, 2, 0), (1, 1, 0, 2, 0), (2, 0, 0, 2, 1), (3, 2, 5, 0, 0), (4, 4, 0, 1, 2), (4, 3, 7, 3, 0),
-    (6, 8, 9, 2, 3), (32, 63, 0, 2, 0), (1, 0, 3, 5, 0), (6, 4, 4, 2, 0), (6, 1, 1, 0, 5), (0, 2, 2, 1, 3),
-    (8, 3, 3, 9, 1), (6, 4, 4, 0, 0), (5, 6, 6, 1, 3), (0, 0, 0, 1, 2)])
-def test_pass_schedule_invariance(snapgpu, oracle_mod, synth_mod, seeds, limit, limit2, rounds, vseeds):
+@pytest.mark.parametrize("seeds,limit,limit2,rounds,vseeds,chunk", [
+    (0, 0, 0, 2, 0, 0), (1, 1, 0, 2, 0, 0), (2, 0, 0, 2, 1, 0), (3, 2, 5, 0, 0, 0), (4, 4, 0, 1, 2, 0),
+    (4, 3, 7, 3, 0, 0), (6, 8, 9, 2, 3, 0), (32, 63, 0, 2, 0, 0), (1, 0, 3, 5, 0, 0), (6, 4, 4, 2, 0, 0),
+    (6, 1, 1, 0, 5, 0), (0, 2, 2, 1, 3, 0), (8, 3, 3, 9, 1, 0), (6, 4, 4, 0, 0, 0), (5, 6, 6, 1, 3, 0),
+    (0, 0, 0, 1, 2, 0), (5, 6, 6, 1, 0, 1000), (5, 6, 6, 1, 0, 2500), (0, 0, 0, 2, 0, 1500),
+    (6, 4, 4, 0, 3, 700), (5, 6, 6, 1, 0, 7)])
+def test_pass_schedule_invariance(snapgpu, oracle_mod, synth_mod, seeds, limit, limit2, rounds, vseeds, chunk):
     """The pass schedule (stage seeds, first verify limits, exact-request rounds, seeds covered by
-    the first verification) never changes outputs."""
+    the first verification, reads per chunk and so one or two workers) never changes outputs."""
     from synth.workloads import MID
     w, g, reads = _world(synth_mod, MID, 1_000_000, 6_000)
     old = snapgpu.get_tuning()
     try:
-        snapgpu.set_tuning(seeds, limit, limit2, 0, rounds, vseeds)
-        _check(snapgpu, oracle_mod, w, g, reads, f"schedule {seeds}/{limit}/{limit2}/{rounds}/{vseeds}")
+        snapgpu.set_tuning(seeds, limit, limit2, 0, rounds, vseeds, chunk)
+        _check(snapgpu, oracle_mod, w, g, reads, f"schedule {seeds}/{limit}/{limit2}/{rounds}/{vseeds}/{chunk}")
     finally:
         snapgpu.set_tuning(*old)
 
@@ -259,3 +261,23 @@ def test_mid_full_size_sampled(snapgpu, oracle_mod, synth_mod):
     assert nbad == 0, rep
     calls = np.bincount(gout[4], minlength=3)
     say(f"  calls not/single/multi = {calls.tolist()}")
+
+
+@pytest.mark.gpu
+def test_two_chunk_workers(snapgpu, oracle_mod, synth_mod):
+    """A batch of several chunks with a workspace for two chunk parts is worked by two
+    host threads with a stream each; outputs equal the oracle's."""
+    from synth.workloads import MID
+    w, g, reads = _world(synth_mod, MID, 1_000_000, 8_000)
+    old = snapgpu.get_tuning()
+    try:
+        snapgpu.set_tuning(5, 6, 6, 0, 1, 0, 1500)
+        snapgpu.profile_begin()
+        _check(snapgpu, oracle_mod, w, g, reads, "two workers, chunks of 1500 reads")
+        ctr = snapgpu.profile_counters()
+        snapgpu.profile_end()
+        say(f"counters {ctr}")
+        assert ctr["workers"] == 2, ctr
+        assert ctr["passes"] >= 6, ctr
+    finally:
+        snapgpu.set_tuning(*old)
