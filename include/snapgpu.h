@@ -172,9 +172,10 @@ typedef struct {
     int32_t verify_seeds;   /* snap_align, reads in the lane tile: the first verification covers only
                                locations hit by one of the first verify_seeds seed slots, the others
                                are verified when a replay asks (0 = all locations) */
-    int32_t chunk_reads;    /* reads per chunk pass (0 = 2^20); a batch of several chunks is worked
-                               by two host threads with a stream each when the workspace holds two
-                               chunk parts */
+    int32_t chunk_reads;    /* reads per chunk pass (0 = 2^20) */
+    int32_t workers;        /* a batch of several chunks is worked by up to this many host threads
+                               with a stream each (0 = 2, at most 4), as many as the workspace holds
+                               chunk parts for */
 } snap_tuning;
 
 int snap_set_tuning(const snap_tuning *t);

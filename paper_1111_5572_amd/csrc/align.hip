@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -1988,10 +1989,11 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {5, 6, 6, 0, 1, 0, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
+snap_tuning g_tune = {5, 6, 6, 0, 1, 0, 0, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
                                         // exact-request rounds, first-verification seeds
 
 constexpr int KCAP_NONE = 1 << 20;
+constexpr int MAX_WORKERS = 4;   // chunk workers of one call (host thread + stream each)
 
 // Streams (default priority, non-blocking) kept per device for the second worker of
 // snap_align calls; a call leases one with an event and returns both when it ends.
@@ -2042,7 +2044,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0 || t->chunk_reads < 0) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0 || t->chunk_reads < 0 || t->workers < 0) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -2083,7 +2085,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
-    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0 || tune.chunk_reads < 0) return SNAP_EINVAL;
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0 || tune.chunk_reads < 0 || tune.workers < 0) return SNAP_EINVAL;
     const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
     const int exact_rounds = tune.exact_rounds;
     const int verify_seeds = tune.verify_seeds;
@@ -2143,19 +2145,20 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     // with room for the hits of a typical chunk: one worker's host waits and small
     // kernels then overlap the other's work
     int workers = 1;
-    if (n_reads > R) {
-        Layout l2 = make_layout(n_reads, B, NS, rule.hmax, R, 0, 2);
-        if (l2.total <= ws_bytes) {
-            const int64_t extra = (int64_t)((ws_bytes - l2.total) / (2 * POOL_SLOT_BYTES));
-            l2 = make_layout(n_reads, B, NS, rule.hmax, R, l2.pool_slots + extra, 2);
-            while (l2.total > ws_bytes) {
-                const int64_t over = (int64_t)((l2.total - ws_bytes) / (2 * POOL_SLOT_BYTES)) + 64;
-                l2 = make_layout(n_reads, B, NS, rule.hmax, R, l2.pool_slots - over, 2);
-            }
-            if (l2.pool_slots >= 16 * R) {
-                l = l2;
-                workers = 2;
-            }
+    const int max_workers = std::min<int64_t>(tune.workers > 0 ? tune.workers : 2, (n_reads + R - 1) / R);
+    for (int w = std::min(max_workers, MAX_WORKERS); w >= 2; w--) {
+        Layout lw = make_layout(n_reads, B, NS, rule.hmax, R, 0, w);
+        if (lw.total > ws_bytes) continue;
+        const int64_t extra = (int64_t)((ws_bytes - lw.total) / ((size_t)w * POOL_SLOT_BYTES));
+        lw = make_layout(n_reads, B, NS, rule.hmax, R, lw.pool_slots + extra, w);
+        while (lw.total > ws_bytes) {
+            const int64_t over = (int64_t)((lw.total - ws_bytes) / ((size_t)w * POOL_SLOT_BYTES)) + 64;
+            lw = make_layout(n_reads, B, NS, rule.hmax, R, lw.pool_slots - over, w);
+        }
+        if (lw.pool_slots >= 16 * R) {
+            l = lw;
+            workers = w;
+            break;
         }
     }
     uint32_t *rcode = (uint32_t *)(ws + l.off_rcode);
@@ -2189,7 +2192,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         uint32_t *short_list, *long_list;
         int16_t *rq;
     };
-    Worker wk[2];
+    Worker wk[MAX_WORKERS];
     for (int w = 0; w < workers; w++) {
         char *cb = ws + l.chunk_base + (size_t)w * l.chunk_bytes;
         Worker &W = wk[w];
@@ -2232,17 +2235,18 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0) cus = c;
         steal_waves = (int64_t)cus * 8;
     }
-    // the second worker's stream, from a pool of the device's streams; it starts once
+    // the other workers' streams, from a pool of the device's streams; they start once
     // the read stream is packed on the caller's stream
     wk[0].st = st;
     if (g_prof_on) {
         std::lock_guard<std::mutex> g(g_prof_mu);
         g_ctr.workers = std::max<int64_t>(g_ctr.workers, workers);
     }
-    StreamLease lease(workers > 1 ? dev : -1);
-    if (workers > 1) {
-        if (!lease.s) return SNAP_EDEVICE;
-        wk[1].st = lease.s;
+    std::vector<std::unique_ptr<StreamLease>> leases;
+    for (int w = 1; w < workers; w++) {
+        leases.emplace_back(new StreamLease(dev));
+        if (!leases.back()->s) return SNAP_EDEVICE;
+        wk[w].st = leases.back()->s;
     }
 
     for (int w = 0; w < workers; w++) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)wk[w].misc, 64, 0u);
@@ -2250,9 +2254,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
         timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk); });
     }
-    if (workers > 1) {
-        HIP_OK(hipEventRecord(lease.ev, st));
-        HIP_OK(hipStreamWaitEvent(wk[1].st, lease.ev, 0));
+    for (int w = 1; w < workers; w++) {
+        HIP_OK(hipEventRecord(leases[w - 1]->ev, st));
+        HIP_OK(hipStreamWaitEvent(wk[w].st, leases[w - 1]->ev, 0));
     }
     // one pass over a list of reads (all reads, or the ones an earlier pass left)
     auto run_pass = [&](const uint32_t *ridx, int64_t list_len, int NSp, int Kcap, int final_pass) -> int {
@@ -2576,17 +2580,22 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         return SNAP_OK;
         };
         if (workers == 1) return work(wk[0]);
-        int rc1 = SNAP_OK;
-        std::thread t1([&] {
-            if (hipSetDevice(dev) != hipSuccess) {
-                rc1 = SNAP_EDEVICE;
-                return;
-            }
-            rc1 = work(wk[1]);
-        });
-        const int rc0 = work(wk[0]);
-        t1.join();
-        return rc0 != SNAP_OK ? rc0 : rc1;
+        int rcs[MAX_WORKERS] = {};
+        std::vector<std::thread> threads;
+        for (int w = 1; w < workers; w++) {
+            threads.emplace_back([&, w] {
+                if (hipSetDevice(dev) != hipSuccess) {
+                    rcs[w] = SNAP_EDEVICE;
+                    return;
+                }
+                rcs[w] = work(wk[w]);
+            });
+        }
+        rcs[0] = work(wk[0]);
+        for (auto &t : threads) t.join();
+        for (int w = 0; w < workers; w++)
+            if (rcs[w] != SNAP_OK) return rcs[w];
+        return SNAP_OK;
     };
 
     // stage 1 (when it is not complete): the first pass1_seeds seeds, locations

@@ -264,20 +264,22 @@ def test_mid_full_size_sampled(snapgpu, oracle_mod, synth_mod):
 
 
 @pytest.mark.gpu
-def test_two_chunk_workers(snapgpu, oracle_mod, synth_mod):
-    """A batch of several chunks with a workspace for two chunk parts is worked by two
-    host threads with a stream each; outputs equal the oracle's."""
+@pytest.mark.parametrize("workers", [2, 3, 4])
+def test_chunk_workers(snapgpu, oracle_mod, synth_mod, workers):
+    """A batch of several chunks with a workspace for several chunk parts is worked by
+    that many host threads with a stream each; outputs equal the oracle's."""
     from synth.workloads import MID
     w, g, reads = _world(synth_mod, MID, 1_000_000, 8_000)
     old = snapgpu.get_tuning()
     try:
-        snapgpu.set_tuning(5, 6, 6, 0, 1, 0, 1500)
+        snapgpu.set_tuning(5, 6, 6, 0, 1, 0, 1500, workers)
         snapgpu.profile_begin()
-        _check(snapgpu, oracle_mod, w, g, reads, "two workers, chunks of 1500 reads")
+        _check(snapgpu, oracle_mod, w, g, reads, f"{workers} workers, chunks of 1500 reads",
+               ws=1 << 30)
         ctr = snapgpu.profile_counters()
         snapgpu.profile_end()
         say(f"counters {ctr}")
-        assert ctr["workers"] == 2, ctr
+        assert ctr["workers"] == workers, ctr
         assert ctr["passes"] >= 6, ctr
     finally:
         snapgpu.set_tuning(*old)
