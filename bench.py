@@ -80,8 +80,10 @@ def read_traffic(path, kernel, workload, schedule):
             if line and not line.startswith("#") and ":" in line:
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
+        from paper_1111_5572_amd import make_tuning
         sched = tuple(int(x) for x in kv.get("schedule", "").split(",") if x.strip())
-        if kv.get("kernel") == kernel and kv.get("workload") == workload and sched == tuple(schedule):
+        same = make_tuning(sched).astuple() == make_tuning(tuple(schedule)).astuple()
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and same:
             return int(kv["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         pass
