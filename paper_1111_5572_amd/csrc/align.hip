@@ -57,10 +57,12 @@ constexpr int LANE_LMAX = 512;
 constexpr int REQ_WAVE = 0x4000;
 constexpr int REQ_LIMIT_MASK = 0x3FFF;
 constexpr uint32_t REQ_WAVE_READ = 0x80000000u;
-// Replay of reads with more than 64 locations: up to this many are staged in LDS
-// (seed mask, capped distance | verified limit, scored bit), per wave.
+// Replay of reads with more than 64 locations: a wave stages up to HEAVY_LDS_LOCS of
+// them in LDS (seed mask, capped distance | verified limit << 16, scored bit, and
+// for the phase that scores every remaining location the vote count); a read with
+// more works in global memory.
 constexpr int HEAVY_LDS_LOCS = 1024;
-constexpr int HEAVY_LDS_WORDS = 2 * HEAVY_LDS_LOCS + HEAVY_LDS_LOCS / 32;
+__host__ __device__ constexpr int heavy_lds_words(int cap) { return 2 * cap + cap / 32 + cap / 4; }
 // Outcome of a read's replay in a pass.
 constexpr uint8_t RF_DONE = 0;      // outputs written
 constexpr uint8_t RF_PENDING = 1;   // needs a seed this pass did not probe
@@ -1378,11 +1380,12 @@ __device__ inline int ed_answer(int dc, int vl, int lim) {
 // that scores every remaining location only changes state at calls that return a
 // distance, so it scans for the next such location in selection order (vote count
 // descending, then p, then strand) instead of visiting each one.
-// LIGHT: the reads with at most 64 locations (registers); otherwise the others
-// (global memory). Both instantiations run over the same read list.
-template <bool LIGHT>
+// CAP 0: reads with at most 64 locations (registers); otherwise reads with more,
+// staged in LDS when they have at most CAP (global memory beyond).
+template <int CAP>
 __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
-    extern __shared__ uint32_t rsm[];   // heavy instantiation: HEAVY_LDS_WORDS per wave
+    constexpr bool LIGHT = CAP == 0;
+    extern __shared__ uint32_t rsm[];   // heavy instantiations: heavy_lds_words(CAP) per wave
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1488,16 +1491,18 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         } else {
         // ---- reads with more than 64 locations: seed masks, capped distances, limits
         // and scored flags staged in this wave's LDS when they fit, else read in place
-        const bool in_lds = C <= HEAVY_LDS_LOCS;
-        uint32_t *Lmask = rsm + (threadIdx.x >> 6) * HEAVY_LDS_WORDS;
-        uint32_t *Ldv = Lmask + HEAVY_LDS_LOCS;
-        uint32_t *Lsc = Ldv + HEAVY_LDS_LOCS;
+        constexpr int cap = CAP > 0 ? CAP : 32;
+        const bool in_lds = C <= cap;
+        uint32_t *Lmask = rsm + (threadIdx.x >> 6) * heavy_lds_words(cap);
+        uint32_t *Ldv = Lmask + cap;
+        uint32_t *Lsc = Ldv + cap;
+        uint8_t *Llev = reinterpret_cast<uint8_t *>(Lsc + cap / 32);   // remaining phase: vote count
         if (in_lds) {
             for (int64_t k = lane; k < C; k += 64) {
                 Lmask[k] = a.mask[base + k];
                 Ldv[k] = (uint32_t)a.dcap[base + k] | ((uint32_t)(uint16_t)a.vlim[base + k] << 16);
             }
-            for (int w = lane; w < HEAVY_LDS_LOCS / 32; w += 64) Lsc[w] = 0;
+            for (int w = lane; w < cap / 32; w += 64) Lsc[w] = 0;
         } else {
             for (int64_t k = lane; k < C; k += 64) a.scored[base + k] = 0;
         }
@@ -1518,18 +1523,29 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             all_over = false;
             prefix |= 1u << i;
             if (i < round0) t++;
-            // the unscored location with the most seeds hitting; ties to smaller p, then +
-            int64_t kb = -1;
-            uint32_t bv = 0;
-            for (int64_t c0 = 0; c0 < C; c0 += 64) {
-                const int64_t k = c0 + lane;
-                uint32_t v = 0;
-                if (k < C && !scored_at(k)) v = (uint32_t)__builtin_popcount(mask_at(k) & prefix);
-                const int j = wave_argmax6(v);
-                if (j >= 0) {
-                    const uint32_t vj = (uint32_t)lane_i32((int)v, j);
-                    if (vj > bv) { bv = vj; kb = c0 + j; }
+            // the unscored location with the most seeds hitting; ties to smaller p, then +:
+            // each lane keeps the first best of its locations (k = lane + 64 j), then the wave
+            // takes the highest vote and, among the lanes holding it, the lowest location
+            // (one ballot per bit of each)
+            uint32_t lv = 0, lk = 0xFFFFFFFFu;
+            for (int64_t k = lane; k < C; k += 64) {
+                if (!scored_at(k)) {
+                    const uint32_t v = (uint32_t)__builtin_popcount(mask_at(k) & prefix);
+                    if (v > lv) { lv = v; lk = (uint32_t)k; }
                 }
+            }
+            int64_t kb = -1;
+            uint64_t alive = __ballot(lv != 0);
+            if (alive) {
+                for (int b = 5; b >= 0; b--) {
+                    const uint64_t hb = alive & __ballot((lv >> b) & 1u);
+                    if (hb) alive = hb;
+                }
+                for (int b = 31 - __builtin_clz((uint32_t)C); b >= 0; b--) {
+                    const uint64_t hb = alive & __ballot(((lk >> b) & 1u) == 0);
+                    if (hb) alive = hb;
+                }
+                kb = (int64_t)(uint32_t)lane_i32((int)lk, __builtin_ctzll(alive));
             }
             if (kb >= 0) {
                 const int lim = d_limit(st, dmax, c);
@@ -1561,13 +1577,20 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                 break;
             }
             if (st.d_best < DINF && t >= st.d_best + c) {
-                // score every remaining location; vote counts are frozen now
+                // score every remaining location; vote counts are frozen now (kept per
+                // location in LDS, 0 for a scored one)
+                if (in_lds) {
+                    for (int64_t k = lane; k < C; k += 64)
+                        Llev[k] = scored_at(k) ? 0 : (uint8_t)__builtin_popcount(mask_at(k) & prefix);
+                    __builtin_amdgcn_wave_barrier();
+                }
                 for (int lev = __builtin_popcount(prefix); lev >= 1 && !unresolved; lev--) {
                     for (int64_t c0 = 0; c0 < C && !unresolved; c0 += 64) {
                         const int64_t k = c0 + lane;
                         bool in = false;
                         int dc = 0, vl = 0;
-                        if (k < C && !scored_at(k) && __builtin_popcount(mask_at(k) & prefix) == lev) {
+                        if (k < C && (in_lds ? (int)Llev[k] == lev
+                                             : !scored_at(k) && __builtin_popcount(mask_at(k) & prefix) == lev)) {
                             in = true;
                             dc = dc_at(k);
                             vl = vl_at(k);
@@ -2456,8 +2479,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
-                          rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax, pos, strand,
-                          dist, second, call};
+                          rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax,
+                          pos, strand, dist, second, call};
             const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
             // reads with up to TINY_LOCS locations replay a lane each; the others, a wave
             // each, from their own lists (up to 64 locations in registers, more in LDS)
@@ -2469,15 +2492,16 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     ReplayArgs l = x;
                     l.rlist = light_list;
                     l.rlist_n = sel_n + 8;
-                    timed("replay", st, [&] { hipLaunchKernelGGL(k_replay<true>, dim3(blocks), dim3(256), 0, st, l); });
+                    timed("replay", st, [&] { hipLaunchKernelGGL(k_replay<0>, dim3(blocks), dim3(256), 0, st, l); });
                 }
                 if (maxH > 64) {
-                    (void)select_count_range(sel_tmp, sel_tb, items, x.rlist, ccount, 64u, 0xFFFFFFFFu, heavy_list, sel_n + 4, st);
+                    (void)select_count_range(sel_tmp, sel_tb, items, x.rlist, ccount, 64u, 0xFFFFFFFFu, heavy_list,
+                                             sel_n + 4, st);
                     ReplayArgs h = x;
                     h.rlist = heavy_list;
                     h.rlist_n = sel_n + 4;
                     const unsigned hb = (unsigned)std::min<int64_t>((items + 3) / 4, 1024);
-                    timed("replay_heavy", st, [&] { hipLaunchKernelGGL(k_replay<false>, dim3(hb), dim3(256), (size_t)4 * 4 * HEAVY_LDS_WORDS, st, h); });
+                    timed("replay_heavy", st, [&] { hipLaunchKernelGGL(k_replay<HEAVY_LDS_LOCS>, dim3(hb), dim3(256), (size_t)4 * 4 * heavy_lds_words(HEAVY_LDS_LOCS), st, h); });
                 }
             };
             replay(ra, rb, nr);
