@@ -892,15 +892,12 @@ struct WaveVerifyArgs {
     Pass ps;
     const uint64_t *key;
     const uint32_t *cread;
-    const uint32_t *list;       // locations of this class (null: all)
-    const int64_t *nlist_ptr;   // how many (or the number of locations when list is null)
     Rule rule;
     int32_t RW, TW, KL;         // staged words (guard included) and the largest limit
     uint16_t *dcap;
     int16_t *vlim;
     uint32_t *steps;
     unsigned long long *next;   // shared work counter (work-stealing launches), null: static stride
-    int32_t grab;               // locations taken per grab
     int16_t *rq;                // requested limit per location, tagged REQ_WAVE (null: the read's limit);
                                 // cleared once verified
 };
@@ -1001,28 +998,6 @@ __device__ inline void verify_loc_wave(const WaveVerifyArgs &a, int64_t k, uint3
     __syncthreads();
 }
 
-__device__ inline void verify_one_wave(const WaveVerifyArgs &a, int64_t idx, uint32_t *sm) {
-    verify_loc_wave(a, a.list ? (int64_t)a.list[idx] : idx, sm);
-}
-
-__global__ __launch_bounds__(64) void k_verify_wave(WaveVerifyArgs a) {
-    extern __shared__ uint32_t wsm[];
-    const int64_t n = *a.nlist_ptr;
-    if (!a.next) {
-        for (int64_t idx = blockIdx.x; idx < n; idx += gridDim.x) verify_one_wave(a, idx, wsm);
-        return;
-    }
-    for (;;) {
-        unsigned long long first = 0;
-        if (threadIdx.x == 0) first = atomicAdd(a.next, (unsigned long long)a.grab);
-        first = __shfl((unsigned long long)first, 0, 64);
-        if ((int64_t)first >= n) break;
-        const int64_t last = min((int64_t)first + a.grab, n);
-        for (int64_t idx = (int64_t)first; idx < last; idx++) verify_one_wave(a, idx, wsm);
-    }
-}
-
-
 // Verification requests of the reads being replayed.
 struct RequestArgs {
     const uint32_t *rlist;      // chunk reads being replayed
@@ -1080,14 +1055,13 @@ __global__ __launch_bounds__(64) void k_verify_requests_wave(WaveVerifyArgs a, R
     }
 }
 
-// Batched form: one persistent launch verifies every location of a pass. Each wave
-// first takes long locations one at a time (wave tile), then groups of 64 short
-// locations (lane tile) in guided chunks of about half the remaining groups
-// divided by the number of waves, at least one (the range rule of Section 2.3).
+// Batched form: one persistent launch gives every short location of a pass its first
+// verification (long reads' locations are verified on request). Each wave takes
+// groups of 64 locations (lane tile) in guided chunks of about half the remaining
+// groups divided by the number of waves, at least one (the range rule of Section 2.3).
 struct StealArgs {
     VerifyArgs va;               // lane tile over the short list
-    WaveVerifyArgs wa;           // wave tile over the long list
-    unsigned long long *next;    // [0] long cursor, [1] short-group cursor
+    unsigned long long *next;    // [1]: group cursor
     int32_t nwaves;
 };
 
@@ -1095,14 +1069,6 @@ template <int KMAX>
 __global__ __launch_bounds__(64) void k_verify_steal(StealArgs a) {
     extern __shared__ uint32_t ssm[];
     const int lane = threadIdx.x;
-    const int64_t nlong = *a.wa.nlist_ptr;
-    for (;;) {
-        unsigned long long i = 0;
-        if (lane == 0) i = atomicAdd(&a.next[0], 1ull);
-        i = __shfl(i, 0, 64);
-        if ((int64_t)i >= nlong) break;
-        verify_one_wave(a.wa, (int64_t)i, ssm);
-    }
     const int64_t nshort = *a.va.nlist_ptr;
     const int64_t ngroups = (nshort + 63) / 64;
     for (;;) {
@@ -2330,7 +2296,6 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         int64_t *sel_n = misc + 20;   // selected counts: [2] reads to replay, [3] reads for the next pass, ...
         unsigned long long *route_cnt = (unsigned long long *)(misc + 8);   // two counters
         unsigned long long *steal_next = (unsigned long long *)(misc + 10);  // two cursors
-        const int64_t *zero_count = (const int64_t *)(misc + 14);
         // per-location step counts reuse the hit array, dead once locations are compacted
         uint32_t *steps = g_prof_on ? (uint32_t *)hk : nullptr;
         for (;;) {
@@ -2431,19 +2396,16 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, ncand,
                               rule, RW, TW, dcap, vlim, steps, slist, nshort};
                 // long locations are verified on request, with the exact limit
-                const int64_t *nlong = (const int64_t *)(route_cnt + 1);
                 if (!all_lane) {
+                    const int64_t *nlong = (const int64_t *)(route_cnt + 1);
                     timed("mark", st, [&] { hipLaunchKernelGGL(k_mark_unverified, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, long_list, nlong, dcap, vlim, steps); });
-                    nlong = zero_count;
                 }
-                WaveVerifyArgs wa{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
-                                  long_list, nlong, rule, RWL, TWL, Kw, dcap, vlim, steps, nullptr, 1, nullptr};
                 if (batched) {
-                    // one persistent work-stealing launch for both tiles
+                    // one persistent work-stealing launch over the short locations
                     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 4, 0u);
                     const int nwaves = (int)std::min<int64_t>(std::max<int64_t>((total + 63) / 64, 1), steal_waves);
-                    StealArgs sa{va, wa, steal_next, nwaves};
-                    const size_t lds_s = std::max(lds, lds_wave);
+                    StealArgs sa{va, steal_next, nwaves};
+                    const size_t lds_s = lds;
                     timed("verify_steal", st, [&] {
                         if (kmax_t == 7)
                             hipLaunchKernelGGL(k_verify_steal<7>, dim3(nwaves), dim3(64), lds_s, st, sa);
@@ -2542,8 +2504,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 if (!all_lane) {
                     // wave tile, each location at exactly the limit its read uses there
                     WaveVerifyArgs wq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
-                                      nullptr, nullptr, rule, RWL, TWL, Kw, dcap, vlim, steps,
-                                      batched ? steal_next : nullptr, 1, rq};
+                                      rule, RWL, TWL, Kw, dcap, vlim, steps, batched ? steal_next : nullptr, rq};
                     if (batched) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steal_next, 2, 0u);
                     const unsigned wb = (unsigned)std::min<int64_t>(nrep, steal_waves);
                     timed("verify_request_wave", st, [&] { hipLaunchKernelGGL(k_verify_requests_wave, dim3(wb), dim3(64), lds_wave, st, wq, qa); });
