@@ -907,24 +907,78 @@ __device__ inline uint32_t lds_w16(const uint32_t *A, int i) {
     return funnel(A[w + 1], A[w], (uint32_t)(i & 15) * 2);
 }
 
-__device__ inline int wave_slide(const uint32_t *RC, const uint32_t *RN, const uint32_t *TC, const uint32_t *TN,
-                                 int i, int d, int L, int Tn) {
+// Extend diagonal d from read row i (text column i + d) while bases are equal, 16 per
+// step; the read' and window codes are in LDS, and when either holds an N (HAS_N)
+// the N flags come from the packed 1-bit masks in global memory.
+struct WaveText {
+    const uint32_t *RC, *TC;
+    const uint32_t *rmask, *gmask;
+    int64_t xb, p;
+    int L, Tn, strand;
+};
+
+template <bool HAS_N>
+__device__ inline int wave_slide(const WaveText &w, int i, int d) {
     for (;;) {
         const int j = i + d;
-        const int rem = min(L - i, Tn - j);
+        const int rem = min(w.L - i, w.Tn - j);
         if (rem <= 0) return i;
-        const uint32_t x = lds_w16(RC, i) ^ lds_w16(TC, j);
-        uint32_t m = ((x | (x >> 1)) & 0x55555555u) | lds_w16(RN, i) | lds_w16(TN, j);
+        const uint32_t x = lds_w16(w.RC, i) ^ lds_w16(w.TC, j);
+        uint32_t m = (x | (x >> 1)) & 0x55555555u;
+        if (HAS_N) {
+            const uint32_t rn = w.strand == 0 ? ext_mask16(w.rmask, w.xb + i)
+                                              : __builtin_bitreverse32(ext_mask16(w.rmask, w.xb + w.L - 16 - i)) >> 16;
+            m |= spread16(rn) | spread16(ext_mask16(w.gmask, w.p + j));
+        }
         if (rem < 16) m |= 0xFFFFFFFFu << (2 * rem);
         if (m == 0) { i += 16; continue; }
         return i + (int)(__builtin_ctz(m) >> 1);
     }
 }
 
+// Furthest rows per diagonal for e = 0, 1, ..., K with lanes over diagonals (64 per
+// step), the previous round's rows read from one LDS buffer and the new ones written to
+// the other (16-bit: rows never exceed the read length). D if D <= K, else K + 1.
+template <bool HAS_N>
+__device__ inline int lv_wave(const WaveText &w, int K, int16_t *F0, int16_t *F1, uint32_t &nsteps) {
+    constexpr int NEG = -30000;
+    const int lane = threadIdx.x;
+    const int L = w.L, Tn = w.Tn;
+    for (int t = lane; t < 2 * max(K, 0) + 3; t += 64) { F0[t] = (int16_t)NEG; F1[t] = (int16_t)NEG; }
+    int i0 = 0;
+    if (lane == 0) i0 = wave_slide<HAS_N>(w, 0, 0);
+    i0 = __shfl(i0, 0, 64);
+    if (i0 >= L) return 0;
+    if (lane == 0) F0[K + 1] = (int16_t)i0;
+    __syncthreads();
+    int16_t *prev = F0, *nxt = F1;
+    for (int e = 1; e <= K; e++) {
+        bool hit = false;
+        for (int d = -e + lane; d <= e; d += 64) {
+            const int idx = d + K + 1;
+            int i = max((int)prev[idx - 1], max((int)prev[idx], (int)prev[idx + 1]) + 1);
+            i = min(i, min(L, Tn - d));
+            if (i >= max(0, -d)) {
+                nsteps++;
+                i = wave_slide<HAS_N>(w, i, d);
+                if (i >= L) hit = true;
+            } else {
+                i = NEG;
+            }
+            nxt[idx] = (int16_t)i;
+        }
+        const bool done = __ballot(hit) != 0;
+        __syncthreads();
+        if (done) return e;
+        int16_t *t = prev; prev = nxt; nxt = t;
+    }
+    return K + 1;
+}
+
 __device__ inline void verify_loc_wave(const WaveVerifyArgs &a, int64_t k, uint32_t *sm) {
     const int lane = threadIdx.x;
-    uint32_t *RC = sm, *RN = RC + a.RW, *TC = RN + a.RW, *TN = TC + a.TW;
-    int *F0 = reinterpret_cast<int *>(TN + a.TW), *F1 = F0 + (2 * a.KL + 3);
+    uint32_t *RC = sm, *TC = RC + a.RW;
+    int16_t *F0 = reinterpret_cast<int16_t *>(TC + a.TW), *F1 = F0 + (2 * a.KL + 3);
     const uint64_t key = a.key[k];
     const int64_t p = (int64_t)(key >> 1);
     const int strand = (int)(key & 1);
@@ -935,58 +989,25 @@ __device__ inline void verify_loc_wave(const WaveVerifyArgs &a, int64_t k, uint3
     const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + max(K, 0));
     const int nrw = (L + 15) >> 4, ntw = (Tn + 15) >> 4;
     for (int w = lane; w < nrw; w += 64) {
-        uint32_t c, n;
         if (strand == 0) {
-            c = ext_code16(a.rcode, xb + 16 * w);
-            n = ext_mask16(a.rmask, xb + 16 * w);
+            RC[w] = ext_code16(a.rcode, xb + 16 * w);
         } else {
-            const int64_t x = xb + L - 16 * (w + 1);
-            c = rc16(ext_code16(a.rcode, x));
-            n = __builtin_bitreverse32(ext_mask16(a.rmask, x)) >> 16;
+            RC[w] = rc16(ext_code16(a.rcode, xb + L - 16 * (w + 1)));
         }
-        RC[w] = c;
-        RN[w] = spread16(n);
     }
-    for (int w = lane; w < ntw; w += 64) {
-        TC[w] = ext_code16(a.gcode, p + 16 * w);
-        TN[w] = spread16(ext_mask16(a.gmask, p + 16 * w));
-    }
-    if (lane == 0) { RC[nrw] = 0; RN[nrw] = 0; TC[ntw] = 0; TN[ntw] = 0; }
-    constexpr int NEG = -(1 << 28);
-    for (int t = lane; t < 2 * max(K, 0) + 3; t += 64) { F0[t] = NEG; F1[t] = NEG; }
+    for (int w = lane; w < ntw; w += 64) TC[w] = ext_code16(a.gcode, p + 16 * w);
+    if (lane == 0) { RC[nrw] = 0; TC[ntw] = 0; }
+    // any N in the read or the window (32 flags per word, each lane a few words)
+    uint32_t nn = 0;
+    for (int64_t m = (xb >> 5) + lane; m <= (xb + L - 1) >> 5; m += 64) nn |= a.rmask[m];
+    for (int64_t m = (p >> 5) + lane; m <= (p + Tn - 1) >> 5; m += 64) nn |= a.gmask[m];
+    // the end words may hold flags of neighbouring bases: then the N path is taken for
+    // nothing (same result, slower)
+    const bool has_n = __ballot(nn != 0) != 0;
     __syncthreads();
-    int i0 = 0;
-    if (lane == 0) i0 = wave_slide(RC, RN, TC, TN, 0, 0, L, Tn);
-    i0 = __shfl(i0, 0, 64);
-    int D = K + 1;
+    const WaveText w{RC, TC, a.rmask, a.gmask, xb, p, L, Tn, strand};
     uint32_t nsteps = 1;
-    if (i0 >= L) {
-        D = 0;
-    } else {
-        if (lane == 0) F0[K + 1] = i0;
-        __syncthreads();
-        int *prev = F0, *nxt = F1;
-        for (int e = 1; e <= K; e++) {
-            bool hit = false;
-            for (int d = -e + lane; d <= e; d += 64) {
-                const int idx = d + K + 1;
-                int i = max(prev[idx - 1], max(prev[idx], prev[idx + 1]) + 1);
-                i = min(i, min(L, Tn - d));
-                if (i >= max(0, -d)) {
-                    nsteps++;
-                    i = wave_slide(RC, RN, TC, TN, i, d, L, Tn);
-                    if (i >= L) hit = true;
-                } else {
-                    i = NEG;
-                }
-                nxt[idx] = i;
-            }
-            const bool done = __ballot(hit) != 0;
-            __syncthreads();
-            if (done) { D = e; break; }
-            int *t = prev; prev = nxt; nxt = t;
-        }
-    }
+    const int D = has_n ? lv_wave<true>(w, K, F0, F1, nsteps) : lv_wave<false>(w, K, F0, F1, nsteps);
     if (a.steps) {
         for (int d = 32; d >= 1; d >>= 1) nsteps += __shfl_xor(nsteps, d, 64);
     }
@@ -1110,34 +1131,6 @@ __global__ void k_mark_unverified(const uint32_t *list, const int64_t *n_ptr, ui
     dcap[k] = 0xFFFF;
     vlim[k] = -1;
     if (steps) steps[k] = 0;
-}
-
-// Split locations by verify tile: lane-per-location when the read and its limit fit
-// one lane's LDS arrays, wave-per-location otherwise.
-__global__ void k_route(const uint32_t *cread, const int32_t *len, Pass ps, Rule rule, const int64_t *ncand_ptr,
-                        int lane_lmax, int lane_kmax, uint32_t *short_list, uint32_t *long_list,
-                        unsigned long long *counts) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = k < *ncand_ptr;
-    bool is_long = false;
-    if (valid) {
-        const int L = len[gid(ps, cread[k])];
-        const int K = min(dmax_for_length(rule, L) + rule.c - 1, ps.Kcap);
-        is_long = L > lane_lmax || K > lane_kmax;
-    }
-    // one atomic per wave and class
-    const int lane = threadIdx.x & 63;
-    const uint64_t bl = __ballot(valid && is_long), bs = __ballot(valid && !is_long);
-    unsigned long long baseL = 0, baseS = 0;
-    if (lane == 0) {
-        if (bl) baseL = atomicAdd(&counts[1], (unsigned long long)__popcll(bl));
-        if (bs) baseS = atomicAdd(&counts[0], (unsigned long long)__popcll(bs));
-    }
-    baseL = __shfl(baseL, 0, 64);
-    baseS = __shfl(baseS, 0, 64);
-    const uint64_t below = (1ull << lane) - 1;
-    if (valid && is_long) long_list[baseL + __popcll(bl & below)] = (uint32_t)k;
-    if (valid && !is_long) short_list[baseS + __popcll(bs & below)] = (uint32_t)k;
 }
 
 __global__ void k_sum_u32(const uint32_t *v, const int64_t *n_ptr, unsigned long long *out) {
@@ -1836,6 +1829,24 @@ hipError_t select_idx(void *tmp, size_t &tmp_bytes, int64_t items, P pred, uint3
     return hipcub::DeviceSelect::If(tmp, tmp_bytes, ci, out, nsel, (int)items, pred, st);
 }
 
+// Locations (below the chunk's count) of the lane tile, or of the wave tile: a lane
+// per location when the read and its limit fit one lane's LDS arrays.
+struct TilePred {
+    const uint32_t *cread;
+    const int32_t *len;
+    Pass ps;
+    Rule rule;
+    const int64_t *ncand;
+    int32_t lane_lmax, lane_kmax;
+    bool want_long;
+    __device__ bool operator()(uint32_t k) const {
+        if ((int64_t)k >= *ncand) return false;
+        const int L = len[gid(ps, cread[k])];
+        const int K = min(dmax_for_length(rule, L) + rule.c - 1, ps.Kcap);
+        return (L > lane_lmax || K > lane_kmax) == want_long;
+    }
+};
+
 // Reads whose hit count is in (lo, hi].
 struct HitRangePred {
     const uint32_t *hits;
@@ -1874,6 +1885,9 @@ size_t select_tmp_bytes(int64_t items) {
     (void)select_idx(nullptr, a, items, FlagPred{nullptr, 0}, nullptr, nullptr, 0);
     (void)select_count_range(nullptr, b, items, nullptr, nullptr, 0, 0, nullptr, nullptr, 0);
     (void)select_idx(nullptr, c, items, FirstSeedsPred{nullptr, nullptr, 0}, nullptr, nullptr, 0);
+    size_t e = 0;
+    (void)select_idx(nullptr, e, items, TilePred{}, nullptr, nullptr, 0);
+    c = std::max(c, e);
     size_t d = 0;
     (void)select_idx(nullptr, d, items, HitRangePred{nullptr, 0, 0}, nullptr, nullptr, 0);
     return std::max(std::max(a, d), std::max(b, c));
@@ -2222,7 +2236,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     {
         int c = 0;
         if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0) cus = c;
-        steal_waves = (int64_t)cus * 8;
+        steal_waves = (int64_t)cus * 16;
     }
     // the other workers' streams, from a pool of the device's streams; they start once
     // the read stream is packed on the caller's stream
@@ -2262,7 +2276,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int Kw = Kmax;
         const int RWL = (std::max(maxL, 1) + 15) / 16 + 1;
         const int TWL = (std::max(maxL, 1) + Kw + 15) / 16 + 1;
-        const size_t lds_wave = (size_t)4 * (2 * RWL + 2 * TWL) + (size_t)8 * (2 * Kw + 3);
+        const size_t lds_wave = (size_t)4 * (RWL + TWL) + (size_t)4 * (2 * Kw + 3);
         if (lds > (size_t)lds_max || (!all_lane && lds_wave > (size_t)lds_max)) return SNAP_EINVAL;
         // workers take ranges of R reads of the list in turn; a range whose hits do not
         // fit the pool is done in several chunks
@@ -2387,11 +2401,13 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 const uint32_t *slist = nullptr;
                 const int64_t *nshort = ncand;
                 if (!all_lane) {
-                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)route_cnt, 4, 0u);
-                    timed("route", st, [&] { hipLaunchKernelGGL(k_route, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, cread, lengths, ps, rule,
-                                       ncand, lane_lmax, LANE_KMAX, short_list, long_list, route_cnt); });
+                    int64_t *rc64 = (int64_t *)route_cnt;
+                    HIP_OK(select_idx(sel_tmp, sel_tb, total, TilePred{cread, lengths, ps, rule, ncand, lane_lmax, LANE_KMAX, false},
+                                      short_list, rc64, st));
+                    HIP_OK(select_idx(sel_tmp, sel_tb, total, TilePred{cread, lengths, ps, rule, ncand, lane_lmax, LANE_KMAX, true},
+                                      long_list, rc64 + 1, st));
                     slist = short_list;
-                    nshort = (const int64_t *)route_cnt;
+                    nshort = rc64;
                 }
                 VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, ncand,
                               rule, RW, TW, dcap, vlim, steps, slist, nshort};
