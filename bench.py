@@ -43,6 +43,8 @@ def log(*a):
 
 def roofline_of(kern, ctr, prefer=None):
     """Roofline entry of the dominant kernel (or `prefer` if given)."""
+    if prefer is not None and prefer not in kern:
+        return None
     dom = prefer if prefer in kern else max(kern.items(), key=lambda kv: kv[1][1])[0]
     launches, total_ms = kern[dom]
     avg_s = total_ms / 1000.0 / launches
@@ -68,6 +70,13 @@ def roofline_of(kern, ctr, prefer=None):
     achieved = work / avg_s
     return {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 5), "avg_launch_ms": round(total_ms / launches, 4), "launches": launches}
+
+
+def phases_of(kern, ctr):
+    """Roofline entries of the gather phase (HBM) and of the longest verify kernel (VALU)."""
+    ver = [k for k in kern if k.startswith("verify")]
+    vdom = max(ver, key=lambda k: kern[k][1]) if ver else None
+    return {"gather": roofline_of(kern, ctr, "gather"), "verify": roofline_of(kern, ctr, vdom) if vdom else None}
 
 
 def read_traffic(path, kernel, workload, schedule):
@@ -251,6 +260,8 @@ def bench_batched(args, w, dev):
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
         "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
         "roofline": roofline,
+        # the two phases the method hinges on: gather (HBM-bound) and verify (VALU-bound)
+        "phases": phases_of(kern, ctr),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -541,6 +552,8 @@ def main():
         "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
         "schedule": tune_info,
         "roofline": roofline,
+        # the two phases the method hinges on: gather (HBM-bound) and verify (VALU-bound)
+        "phases": phases_of(kern, ctr),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
