@@ -41,6 +41,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def build_index(g, seed_len):
+    """Device index of the genome; logs each finished build stage (a large genome
+    takes minutes on the host)."""
+    t0 = time.time()
+    return snapgpu.Index(g, seed_len, progress=lambda stage: log(f"  index: {stage} ({time.time() - t0:.1f}s)"))
+
+
 def roofline_of(kern, ctr, prefer=None):
     """Roofline entry of the dominant kernel (or `prefer` if given)."""
     if prefer is not None and prefer not in kern:
@@ -151,7 +158,7 @@ def bench_batched(args, w, dev):
     reads = w.make_reads(g)
     log(f"reads: {reads.n} ({int(reads.bases.shape[0])} bases) in {time.time() - t:.1f}s")
     t = time.time()
-    gix = snapgpu.Index(g, w.params.seed_len)
+    gix = build_index(g, w.params.seed_len)
     index_s = time.time() - t
     sizes = gix.sizes()
     log(f"index built and resident in {index_s:.1f}s: {sizes}")
@@ -280,7 +287,7 @@ def bench_served(args, w, dev):
     pool = w.make_reads(g)
     log(f"genome {len(g)} bases, read pool {pool.n} reads in {time.time() - t:.1f}s")
     t = time.time()
-    gix = snapgpu.Index(g, w.params.seed_len)
+    gix = build_index(g, w.params.seed_len)
     log(f"index resident in {time.time() - t:.1f}s")
     params = snapgpu.params_from(w.params)
     # the batched form's schedule for this length mix, when the tuning table has it
@@ -442,7 +449,7 @@ def main():
     reads = w.make_reads(g)
     log(f"reads: {reads.n} ({int(reads.bases.shape[0])} bases) in {time.time() - t:.1f}s")
     t = time.time()
-    gix = snapgpu.Index(g, w.params.seed_len)
+    gix = build_index(g, w.params.seed_len)
     index_s = time.time() - t
     sizes = gix.sizes()
     log(f"index built and resident in {index_s:.1f}s: {sizes}")
@@ -542,7 +549,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded genome and simulated reads; no real data)",
         "config": {"workload": w.name, "genome_bases": len(g), "reads": reads.n,
-                   "read_len": int(reads.lengths.max()), "seed_len": w.params.seed_len,
+                   "read_len": (int(reads.lengths.max()) if reads.lengths.min() == reads.lengths.max()
+                                else f"{int(reads.lengths.min())}-{int(reads.lengths.max())}"),
+                   "seed_len": w.params.seed_len,
                    "seeds_per_read": w.params.n_min, "d_max": w.params.d_max, "conf_c": w.params.conf_c,
                    "max_hits": w.params.max_hits},
         "gbases_per_s": round(gbases_per_s, 4),

@@ -71,6 +71,13 @@ typedef struct {
  */
 int snap_index_build(const uint8_t *genome, uint64_t len, int32_t seed_len, snap_index **out);
 
+/* Same, reporting each finished build stage (packing, records, each radix-sort pass,
+ * grouping, placement, copy to the device) to `progress` (stage text, valid during
+ * the call; `ctx` passed through) from the calling thread. progress may be NULL. */
+typedef void (*snap_progress_fn)(const char *stage, void *ctx);
+int snap_index_build_progress(const uint8_t *genome, uint64_t len, int32_t seed_len, snap_progress_fn progress,
+                              void *ctx, snap_index **out);
+
 /* Release the index and its device memory. NULL is accepted. */
 int snap_index_free(snap_index *ix);
 

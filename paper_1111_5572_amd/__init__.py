@@ -120,6 +120,8 @@ def lib():
         L.snap_strerror.restype = ctypes.c_char_p
         L.snap_index_build.argtypes = [P, u64, i32, ctypes.POINTER(P)]
         L.snap_index_build.restype = ctypes.c_int
+        L.snap_index_build_progress.argtypes = [P, u64, i32, PROGRESS_FN, P, ctypes.POINTER(P)]
+        L.snap_index_build_progress.restype = ctypes.c_int
         L.snap_index_free.argtypes = [P]
         L.snap_index_free.restype = ctypes.c_int
         L.snap_index_info.argtypes = [P, ctypes.POINTER(IndexSizes)]
@@ -204,13 +206,22 @@ def _np_u8(x) -> np.ndarray:
     return np.ascontiguousarray(x, dtype=np.uint8)
 
 
-class Index:
-    """Device-resident seed index of a genome (snap_index_build)."""
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_void_p)
 
-    def __init__(self, genome, seed_len: int = 20):
+
+class Index:
+    """Device-resident seed index of a genome (snap_index_build). `progress`, if
+    given, is called with the text of each finished build stage."""
+
+    def __init__(self, genome, seed_len: int = 20, progress=None):
         g = _np_u8(genome)
         h = ctypes.c_void_p()
-        _check(lib().snap_index_build(g.ctypes.data, g.shape[0], seed_len, ctypes.byref(h)), "snap_index_build")
+        if progress is None:
+            _check(lib().snap_index_build(g.ctypes.data, g.shape[0], seed_len, ctypes.byref(h)), "snap_index_build")
+        else:
+            cb = PROGRESS_FN(lambda stage, ctx: progress(stage.decode()))
+            _check(lib().snap_index_build_progress(g.ctypes.data, g.shape[0], seed_len, cb, None, ctypes.byref(h)),
+                   "snap_index_build_progress")
         self._h = h
         self.seed_len = seed_len
         self.genome_len = int(g.shape[0])

@@ -15,9 +15,12 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/snapgpu.h"
@@ -67,9 +70,18 @@ void parallel_for(int64_t n, int threads, F f) {
     for (auto &x : th) x.join();
 }
 
+// Progress of a long build: each finished stage is reported (stage name, null ctx ok).
+struct Progress {
+    snap_progress_fn fn;
+    void *ctx;
+    void operator()(const char *stage) const {
+        if (fn) fn(stage, ctx);
+    }
+};
+
 // Stable LSD radix sort of records by (key, orient), 8-bit digits, parallel
 // histogram + scatter over contiguous input slices.
-void radix_sort(std::vector<Rec> &a, int key_bits, int threads) {
+void radix_sort(std::vector<Rec> &a, int key_bits, int threads, const Progress &prog) {
     const int64_t n = (int64_t)a.size();
     if (n <= 1) return;
     std::vector<Rec> b(n);
@@ -96,18 +108,61 @@ void radix_sort(std::vector<Rec> &a, int key_bits, int threads) {
         std::swap(src, dst);
     };
     pass([](const Rec &r) { return (int)r.orient; });
-    for (int sh = 0; sh < key_bits; sh += 8) pass([sh](const Rec &r) { return (int)((r.key >> sh) & 0xFF); });
+    for (int sh = 0; sh < key_bits; sh += 8) {
+        pass([sh](const Rec &r) { return (int)((r.key >> sh) & 0xFF); });
+        char msg[64];
+        std::snprintf(msg, sizeof(msg), "sorted records by key bits %d-%d", sh, std::min(sh + 8, key_bits) - 1);
+        prog(msg);
+    }
     if (src != a.data()) std::memcpy(a.data(), src, sizeof(Rec) * (size_t)n);
+}
+
+// Host array left uninitialised on allocation (the table is cleared in parallel).
+template <class T>
+struct HostArray {
+    std::unique_ptr<T[]> p;
+    size_t n = 0;
+    void allocate(size_t count) {
+        p.reset(new T[count]);
+        n = count;
+    }
+    size_t size() const { return n; }
+    T *data() { return p.get(); }
+    const T *data() const { return p.get(); }
+    T &operator[](size_t i) { return p[i]; }
+    const T &operator[](size_t i) const { return p[i]; }
+};
+
+// Insert a key into the table: buckets are probed from the key's home bucket on
+// (wrapping at the end) and the first empty slot is claimed with a compare-and-swap
+// on its key word, so threads insert at once. Nothing is ever removed, so every
+// bucket a key passed over is full for good, which is what a lookup relies on (it
+// stops at the first bucket with an empty slot). Which slot a key lands in depends
+// on the order of insertion; what a lookup returns does not.
+void table_insert(uint64_t *table, uint64_t nb, int log2b, uint64_t key, uint64_t val) {
+    uint64_t b = home_bucket(key, log2b);
+    for (;;) {
+        for (int k = 0; k < SLOTS_PER_BUCKET; k++) {
+            uint64_t *slot = table + 2 * (b * SLOTS_PER_BUCKET + k);
+            uint64_t expect = EMPTY_KEY;
+            if (__atomic_load_n(slot, __ATOMIC_RELAXED) == EMPTY_KEY &&
+                __atomic_compare_exchange_n(slot, &expect, key, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+                slot[1] = val;
+                return;
+            }
+        }
+        b = (b + 1) & (nb - 1);
+    }
 }
 
 struct HostIndex {
     std::vector<uint32_t> gcode, gmask, positions;
-    std::vector<uint64_t> table;
+    HostArray<uint64_t> table;
     uint64_t G = 0, nbuckets = 0, windows = 0, distinct = 0;
     int log2b = 0, s = 0;
 };
 
-int build_host(const uint8_t *genome, uint64_t G, int s, HostIndex &h) {
+int build_host(const uint8_t *genome, uint64_t G, int s, HostIndex &h, const Progress &prog) {
     const int T = num_threads();
     h.G = G;
     h.s = s;
@@ -130,6 +185,7 @@ int build_host(const uint8_t *genome, uint64_t G, int s, HostIndex &h) {
             h.gmask[blk] = m;
         }
     });
+    prog("packed the genome");
     // 2. records; windows split into T slices, each slice counted then filled
     const int64_t nwin = (G >= (uint64_t)s) ? (int64_t)(G - s + 1) : 0;
     const uint64_t km = seed_mask(s);
@@ -191,74 +247,72 @@ int build_host(const uint8_t *genome, uint64_t G, int s, HostIndex &h) {
             });
         for (auto &x : th) x.join();
     }
+    prog("emitted window records");
     // 3. sort
-    radix_sort(recs, 2 * s, T);
-    // 4. group: one table entry per distinct canonical code
+    radix_sort(recs, 2 * s, T, prog);
+    // 4. group: one table entry per distinct canonical code. The records are cut
+    //    into T slices at key boundaries; each slice counts its distinct keys, the
+    //    table is sized from the total, then each slice writes its positions and
+    //    inserts its keys.
     h.positions.resize((size_t)nrec);
-    std::vector<uint64_t> keys, vals;
-    for (int64_t i = 0; i < nrec;) {
-        int64_t j = i;
-        uint64_t nf = 0, nr = 0;
-        while (j < nrec && recs[j].key == recs[i].key) {
-            if (recs[j].orient == 0) nf++; else nr++;
-            h.positions[j] = recs[j].q;
-            j++;
-        }
-        keys.push_back(recs[i].key);
-        vals.push_back(((uint64_t)i & OFF_MASK) | ((uint64_t)std::min<uint64_t>(nf, CNT_SAT) << 36) |
-                       ((uint64_t)std::min<uint64_t>(nr, CNT_SAT) << 50));
-        i = j;
+    std::vector<int64_t> cut(T + 1, nrec);
+    cut[0] = 0;
+    for (int t = 1; t < T; t++) {
+        int64_t c = std::max<int64_t>(cut[t - 1], nrec * t / T);
+        while (c > 0 && c < nrec && recs[c].key == recs[c - 1].key) c++;
+        cut[t] = c;
     }
-    h.distinct = keys.size();
-    recs.clear();
-    recs.shrink_to_fit();
+    std::vector<uint64_t> nkeys(T, 0);
+    {
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; t++)
+            th.emplace_back([&, t]() {
+                uint64_t n = 0;
+                for (int64_t i = cut[t]; i < cut[t + 1]; i++)
+                    if (i == cut[t] || recs[i].key != recs[i - 1].key) n++;
+                nkeys[t] = n;
+            });
+        for (auto &x : th) x.join();
+    }
+    h.distinct = 0;
+    for (int t = 0; t < T; t++) h.distinct += nkeys[t];
     // table size: power-of-two buckets, load factor at most 0.7
     uint64_t need = (uint64_t)((double)h.distinct / (0.7 * SLOTS_PER_BUCKET)) + 1;
     h.log2b = 0;
     while ((1ull << h.log2b) < need) h.log2b++;
     h.nbuckets = 1ull << h.log2b;
-    h.table.assign(h.nbuckets * SLOTS_PER_BUCKET * 2, 0);
-    for (uint64_t i = 0; i < h.nbuckets * SLOTS_PER_BUCKET; i++) h.table[2 * i] = EMPTY_KEY;
-    // place keys in home-bucket order (counting sort by home bucket); a key lands
-    // in the first bucket at or after its home that still has a free slot, and
-    // every bucket it passes over is full, which is what the lookup relies on
-    std::vector<uint32_t> home(h.distinct);
-    std::vector<uint64_t> start(h.nbuckets + 1, 0);
-    for (uint64_t i = 0; i < h.distinct; i++) {
-        uint64_t b = home_bucket(keys[i], h.log2b);
-        home[i] = (uint32_t)b;
-        start[b + 1]++;
-    }
-    for (uint64_t b = 0; b < h.nbuckets; b++) start[b + 1] += start[b];
-    std::vector<uint64_t> order(h.distinct);
-    {
-        std::vector<uint64_t> fillp(start.begin(), start.end() - 1);
-        for (uint64_t i = 0; i < h.distinct; i++) order[fillp[home[i]]++] = i;
-    }
-    uint64_t cur = 0, used = 0;
-    std::vector<uint64_t> spill;
-    for (uint64_t k = 0; k < h.distinct; k++) {
-        uint64_t i = order[k], hb = home[i];
-        if (hb > cur) { cur = hb; used = 0; }
-        if (used == SLOTS_PER_BUCKET) { cur++; used = 0; }
-        if (cur >= h.nbuckets) { spill.push_back(i); continue; }
-        uint64_t slot = cur * SLOTS_PER_BUCKET + used++;
-        h.table[2 * slot] = keys[i];
-        h.table[2 * slot + 1] = vals[i];
-    }
-    // keys pushed past the last bucket wrap around to the front
-    for (uint64_t i : spill) {
-        for (uint64_t b = 0;; b++) {
-            uint64_t s0 = b * SLOTS_PER_BUCKET, k;
-            for (k = 0; k < SLOTS_PER_BUCKET; k++)
-                if (h.table[2 * (s0 + k)] == EMPTY_KEY) break;
-            if (k < SLOTS_PER_BUCKET) {
-                h.table[2 * (s0 + k)] = keys[i];
-                h.table[2 * (s0 + k) + 1] = vals[i];
-                break;
-            }
+    h.table.allocate(h.nbuckets * SLOTS_PER_BUCKET * 2);
+    uint64_t *table = h.table.data();
+    parallel_for((int64_t)(h.nbuckets * SLOTS_PER_BUCKET), T, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; i++) {
+            table[2 * i] = EMPTY_KEY;
+            table[2 * i + 1] = 0;
         }
+    });
+    prog("counted distinct keys and cleared the table");
+    {
+        const uint64_t nb = h.nbuckets;
+        const int log2b = h.log2b;
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; t++)
+            th.emplace_back([&, t]() {
+                for (int64_t i = cut[t]; i < cut[t + 1];) {
+                    int64_t j = i;
+                    uint64_t nf = 0, nr = 0;
+                    while (j < cut[t + 1] && recs[j].key == recs[i].key) {
+                        if (recs[j].orient == 0) nf++; else nr++;
+                        h.positions[j] = recs[j].q;
+                        j++;
+                    }
+                    table_insert(table, nb, log2b, recs[i].key,
+                                 ((uint64_t)i & OFF_MASK) | ((uint64_t)std::min<uint64_t>(nf, CNT_SAT) << 36) |
+                                     ((uint64_t)std::min<uint64_t>(nr, CNT_SAT) << 50));
+                    i = j;
+                }
+            });
+        for (auto &x : th) x.join();
     }
+    prog("grouped positions by key and filled the table");
     return SNAP_OK;
 }
 
@@ -278,11 +332,12 @@ bool host_lookup(const HostIndex &h, uint64_t canon, uint64_t *val) {
     return false;
 }
 
-template <class T>
-int upload(const std::vector<T> &v, void **dptr) {
+template <class V>
+int upload(const V &v, void **dptr) {
+    using T = std::remove_cv_t<std::remove_reference_t<decltype(v[0])>>;
     size_t bytes = std::max<size_t>(v.size() * sizeof(T), 256);
     if (hipMalloc(dptr, bytes) != hipSuccess) { *dptr = nullptr; return SNAP_ENOMEM; }
-    if (!v.empty() && hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    if (v.size() != 0 && hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
         return SNAP_EDEVICE;
     return SNAP_OK;
 }
@@ -316,14 +371,20 @@ extern "C" int snap_index_free(snap_index *ix) {
 }
 
 extern "C" int snap_index_build(const uint8_t *genome, uint64_t len, int32_t seed_len, snap_index **out) {
+    return snap_index_build_progress(genome, len, seed_len, nullptr, nullptr, out);
+}
+
+extern "C" int snap_index_build_progress(const uint8_t *genome, uint64_t len, int32_t seed_len,
+                                         snap_progress_fn progress, void *ctx, snap_index **out) {
     if (!out) return SNAP_EINVAL;
+    const Progress prog{progress, ctx};
     *out = nullptr;
     if (!genome || seed_len < 1 || seed_len > 32 || len < (uint64_t)seed_len || len >= (1ull << 32))
         return SNAP_EINVAL;
     HostIndex h;
     int rc;
     try {
-        rc = build_host(genome, len, seed_len, h);
+        rc = build_host(genome, len, seed_len, h, prog);
     } catch (const std::bad_alloc &) {
         return SNAP_ENOMEM;
     }
@@ -336,6 +397,7 @@ extern "C" int snap_index_build(const uint8_t *genome, uint64_t len, int32_t see
         snap_index_free(ix);
         return rc;
     }
+    prog("copied the index to the device");
     ix->d.gcode = (const uint32_t *)ix->alloc_gcode;
     ix->d.gmask = (const uint32_t *)ix->alloc_gmask;
     ix->d.table = (const uint64_t *)ix->alloc_table;
@@ -377,7 +439,7 @@ extern "C" int snap_debug_host_lookup(const uint8_t *genome, uint64_t len, int32
     if (!genome || !queries || !fwd || !rev || seed_len < 1 || seed_len > 32 || len < (uint64_t)seed_len)
         return SNAP_EINVAL;
     HostIndex h;
-    int rc = build_host(genome, len, seed_len, h);
+    int rc = build_host(genome, len, seed_len, h, Progress{nullptr, nullptr});
     if (rc) return rc;
     if (windows) *windows = h.windows;
     for (int64_t i = 0; i < nq; i++) {

@@ -99,3 +99,20 @@ def test_host_table_tandem_counts(snapgpu, oracle_mod, synth_mod):
         assert f == len(ix.occ(s_)) and r == len(ix.occ(s_.translate(comp)[::-1]))
         assert f + r > 300
     ix.close()
+
+
+def test_host_table_single_key(snapgpu, oracle_mod):
+    """A homopolymer genome has one distinct seed: every window groups under one key
+    (the build's parallel grouping must not split a run of equal keys)."""
+    g = "A" * 12_000 + "C" * 25
+    q = ["A" * 20, "T" * 20, "A" * 10 + "C" * 10]
+    windows, got = snapgpu.debug_host_lookup(g, 20, q)
+    ix = oracle_mod.Index(g.encode(), 20)
+    assert windows == ix.windows
+    comp = str.maketrans("ACGT", "TGCA")
+    for s_, (f, r, first) in zip(q, got):
+        occ, rocc = ix.occ(s_), ix.occ(s_.translate(comp)[::-1])
+        assert (f, r) == (len(occ), len(rocc)), s_
+        assert first == (occ[0] if occ else -1)
+    assert got[0][0] == 12_000 - 19
+    ix.close()
