@@ -44,6 +44,7 @@ def log(*a):
 def build_index(g, seed_len):
     """Device index of the genome; logs each finished build stage (a large genome
     takes minutes on the host)."""
+    import paper_1111_5572_amd as snapgpu
     t0 = time.time()
     return snapgpu.Index(g, seed_len, progress=lambda stage: log(f"  index: {stage} ({time.time() - t0:.1f}s)"))
 
