@@ -676,13 +676,15 @@ struct Stage {
     const uint32_t *rmask, *gmask;
     int64_t xb, p;   // read start in the packed stream, window start in the genome
     int L, strand;
-    __device__ inline uint32_t r16(int i) const {
-        int w = i >> 4;
-        return funnel(RC[(w + 1) * 64 + lane], RC[w * 64 + lane], (uint32_t)(i & 15) * 2);
+    // 16 bases of read' and of the window from bit offset b (base b / 2; the funnel
+    // shift takes b mod 32)
+    __device__ inline uint32_t rb(int b) const {
+        int w = b >> 5;
+        return funnel(RC[(w + 1) * 64 + lane], RC[w * 64 + lane], (uint32_t)b);
     }
-    __device__ inline uint32_t t16(int j) const {
-        int w = j >> 4;
-        return funnel(TC[(w + 1) * 64 + lane], TC[w * 64 + lane], (uint32_t)(j & 15) * 2);
+    __device__ inline uint32_t tb(int b) const {
+        int w = b >> 5;
+        return funnel(TC[(w + 1) * 64 + lane], TC[w * 64 + lane], (uint32_t)b);
     }
     // N flags of read' bases [i, i + 16) and window bases [j, j + 16), one per 2-bit slot
     // (bases past the read or the window may carry any value: the caller masks them)
@@ -693,22 +695,27 @@ struct Stage {
     __device__ inline uint32_t tn16(int j) const { return spread16(ext_mask16(gmask, p + j)); }
 };
 
-// Extend a diagonal: from read row i on diagonal d (text column i + d), advance
-// while read and text bases are equal (N equals nothing), 16 bases per step.
+// Rows are kept in bit units (2 bits a base) from here on: the staged words are then
+// indexed by the row itself, and the lowest set bit of the mismatch mask is already
+// an offset in bits (every flag sits on an even bit).
+// Extend a diagonal: from row b on diagonal d (d2 = 2d), advance while read and text
+// bases are equal (N equals nothing), 16 bases per step, up to lim2 = 2 min(L, Tn - d).
+// Bases past the end of the read or window are compared like any others (the staged
+// guard words hold something there); the result is cut back to lim2 instead.
 // HAS_N false: neither the read nor the window holds an N, so the N masks are skipped.
 template <bool HAS_N>
-__device__ __forceinline__ int slide(const Stage &st, int i, int d, int L, int Tn) {
-    for (;;) {
-        const int j = i + d;
-        const int rem = min(L - i, Tn - j);
-        if (rem <= 0) return i;
-        const uint32_t x = st.r16(i) ^ st.t16(j);
-        uint32_t m = (x | (x >> 1)) & 0x55555555u;
-        if (HAS_N) m |= st.rn16(i) | st.tn16(j);
-        if (rem < 16) m |= 0xFFFFFFFFu << (2 * rem);
-        if (m == 0) { i += 16; continue; }
-        return i + (int)(__builtin_ctz(m) >> 1);
+__device__ __forceinline__ int slide2(const Stage &st, int b, int d2, int lim2) {
+    if (b < lim2) {
+        uint32_t run;
+        do {
+            const uint32_t x = st.rb(b) ^ st.tb(b + d2);
+            uint32_t m = (x | (x >> 1)) & 0x55555555u;
+            if (HAS_N) m |= st.rn16(b >> 1) | st.tn16((b + d2) >> 1);
+            run = m ? (uint32_t)__builtin_ctz(m) : 32u;
+            b += (int)run;
+        } while (run == 32u && b < lim2);
     }
+    return min(b, lim2);
 }
 
 // Furthest-reaching rows per diagonal for e = 0, 1, ..., K (the rows of the previous
@@ -717,26 +724,28 @@ template <int KMAX, bool HAS_N>
 __device__ inline int lv_lane(const Stage &st, int L, int Tn, int K, uint32_t &nsteps) {
     constexpr int NEG = -30000;
     const int lane = st.lane;
-    const int i0 = slide<HAS_N>(st, 0, 0, L, Tn);
-    if (i0 >= L) return 0;
+    const int L2 = 2 * L, T2 = 2 * Tn;
+    const int b0 = slide2<HAS_N>(st, 0, 0, min(L2, T2));
+    if (b0 >= L2) return 0;
     for (int t = 0; t < 2 * KMAX + 3; t++) st.FR[t * 64 + lane] = (int16_t)NEG;
-    st.FR[(KMAX + 1) * 64 + lane] = (int16_t)i0;
+    st.FR[(KMAX + 1) * 64 + lane] = (int16_t)b0;
     for (int e = 1; e <= K; e++) {
         int left = NEG;   // previous round's value on diagonal d - 1
         for (int d = -e; d <= e; d++) {
             const int idx = d + KMAX + 1;
             const int od = st.FR[idx * 64 + lane], orr = st.FR[(idx + 1) * 64 + lane];
-            int i = max(left, max(od, orr) + 1);
+            const int lim2 = min(L2, T2 - 2 * d);
+            int b = max(left, max(od, orr) + 2);
             left = od;
-            i = min(i, min(L, Tn - d));
-            if (i >= max(0, -d)) {
+            b = min(b, lim2);
+            if (b >= max(0, -2 * d)) {
                 nsteps++;
-                i = slide<HAS_N>(st, i, d, L, Tn);
-                if (i >= L) return e;
+                b = slide2<HAS_N>(st, b, 2 * d, lim2);
+                if (b >= L2) return e;
             } else {
-                i = NEG;
+                b = NEG;
             }
-            st.FR[idx * 64 + lane] = (int16_t)i;
+            st.FR[idx * 64 + lane] = (int16_t)b;
         }
     }
     return K + 1;
@@ -747,12 +756,13 @@ __device__ inline int lv_lane(const Stage &st, int L, int Tn, int K, uint32_t &n
 template <int KM, bool HAS_N>
 __device__ __forceinline__ int lv_lane_reg(const Stage &st, int L, int Tn, int K, uint32_t &nsteps) {
     constexpr int NEG = -30000;
-    const int i0 = slide<HAS_N>(st, 0, 0, L, Tn);
-    if (i0 >= L) return 0;
+    const int L2 = 2 * L, T2 = 2 * Tn;
+    const int b0 = slide2<HAS_N>(st, 0, 0, min(L2, T2));
+    if (b0 >= L2) return 0;
     int fr[2 * KM + 3];
 #pragma unroll
     for (int t = 0; t < 2 * KM + 3; t++) fr[t] = NEG;
-    fr[KM + 1] = i0;
+    fr[KM + 1] = b0;
     int D = K + 1;
 #pragma unroll
     for (int e = 1; e <= KM; e++) {
@@ -762,17 +772,18 @@ __device__ __forceinline__ int lv_lane_reg(const Stage &st, int L, int Tn, int K
             for (int d = -e; d <= e; d++) {
                 const int idx = d + KM + 1;
                 const int od = fr[idx], orr = fr[idx + 1];
-                int i = max(left, max(od, orr) + 1);
+                const int lim2 = min(L2, T2 - 2 * d);
+                int b = max(left, max(od, orr) + 2);
                 left = od;
-                i = min(i, min(L, Tn - d));
-                if (i >= max(0, -d) && D > K) {
+                b = min(b, lim2);
+                if (b >= max(0, -2 * d) && D > K) {
                     nsteps++;
-                    i = slide<HAS_N>(st, i, d, L, Tn);
-                    if (i >= L) D = e;
+                    b = slide2<HAS_N>(st, b, 2 * d, lim2);
+                    if (b >= L2) D = e;
                 } else {
-                    i = NEG;
+                    b = NEG;
                 }
-                fr[idx] = i;
+                fr[idx] = b;
             }
         }
     }
