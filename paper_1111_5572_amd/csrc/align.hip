@@ -45,6 +45,7 @@ constexpr int ST_NONE = 0;   // slot beyond the read's seeds
 constexpr int ST_N = 1;      // seed holds an N: not looked up
 constexpr int ST_OVER = 2;   // more than h_max index entries: skipped
 constexpr int ST_OK = 3;     // looked up (possibly with no hits)
+static_assert(ST_OK < 4 && MAX_SEEDS <= 32, "a read's seed statuses pack into 64 bits, 2 each");
 constexpr int DINF = 0x3FFF;
 constexpr int STREAM_GUARD = 32;   // bases of padding before the packed read stream
 constexpr int64_t CHUNK_READS = 1 << 20;
@@ -1378,6 +1379,8 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         bool looked = false, all_over = true, ended = false, unresolved = false;
         int64_t need_k = -1;
         uint32_t prefix = 0;
+        // seed slot `lane`'s status, loaded once (the loops over seeds read it by lane)
+        const int stat = lane < NS ? (int)a.pr[r * NS + lane].status : ST_NONE;
         if constexpr (LIGHT) {
             // ---- registers: location `lane`
             const bool have = lane < C;
@@ -1385,7 +1388,6 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             const uint32_t mask = have ? a.mask[base + lane] : 0u;
             const int dc = have ? (int)a.dcap[base + lane] : 0;
             const int vl = have ? (int)a.vlim[base + lane] : 0;
-            const int stat = lane < NS ? (int)a.pr[r * NS + lane].status : ST_NONE;
             bool scored = false;
             uint64_t bmin = ~0ull;
             // bucket representative: first location of the same strand in the run of
@@ -1485,7 +1487,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             return in_lds ? ((Lsc[k >> 5] >> (k & 31)) & 1u) != 0 : a.scored[base + k] != 0;
         };
         for (int i = 0; i < NS; i++) {
-            const int status = a.pr[r * NS + i].status;
+            const int status = lane_i32(stat, i);
             if (status == ST_NONE) { ended = true; break; }
             if (status == ST_N) continue;
             looked = true;
@@ -1692,8 +1694,12 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
         int req_kind = 0, req_lim = 0;   // 0: location need_k at req_lim; 1: undecided at Kfull; 2: remaining at req_lim
         bool looked = false, all_over = true, ended = false, unresolved = false;
         uint32_t prefix = 0, scored = 0;
+        // the seed slots' statuses (2 bits each), loaded together up front
+        uint64_t stw = 0;
+#pragma unroll 4
+        for (int i = 0; i < NS; i++) stw |= (uint64_t)a.pr[r * NS + i].status << (2 * i);
         for (int i = 0; i < NS; i++) {
-            const int status = a.pr[r * NS + i].status;
+            const int status = (int)((stw >> (2 * i)) & 3u);
             if (status == ST_NONE) { ended = true; break; }
             if (status == ST_N) continue;
             looked = true;
