@@ -87,9 +87,19 @@ def phases_of(kern, ctr):
     return {"gather": roofline_of(kern, ctr, "gather"), "verify": roofline_of(kern, ctr, vdom) if vdom else None}
 
 
+def kernel_source_sha1():
+    """SHA-1 of the kernel source file, which a counter summary records: counters taken
+    before the kernels last changed do not describe them."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1111_5572_amd", "csrc", "align.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
 def read_traffic(path, kernel, workload, schedule):
     """HBM bytes per launch from a counter summary ('key: value' lines, '#' comments),
-    when it covers this kernel, workload and pass schedule; else None."""
+    when it covers this kernel, workload and pass schedule and was taken on the kernel
+    source as it is now; else None."""
     try:
         kv = {}
         for line in open(path):
@@ -100,7 +110,8 @@ def read_traffic(path, kernel, workload, schedule):
         from paper_1111_5572_amd import make_tuning
         sched = tuple(int(x) for x in kv.get("schedule", "").split(",") if x.strip())
         same = make_tuning(sched).astuple() == make_tuning(tuple(schedule)).astuple()
-        if kv.get("kernel") == kernel and kv.get("workload") == workload and same:
+        fresh = kv.get("source_sha1") == kernel_source_sha1()
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and same and fresh:
             return int(kv["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         pass
