@@ -72,6 +72,24 @@ def genome_uniform(G: int, seed: int) -> np.ndarray:
     return out
 
 
+def genome_family(G: int, seed: int, copies: int, elem_len: int = 300, div: float = 0.015) -> np.ndarray:
+    """Uniform genome of G bases holding `copies` diverged copies (substitutions at rate
+    div) of one elem_len-base element at random non-overlapping places: a high-copy
+    repeat family, whose reads have as many candidate locations (ASCII uint8)."""
+    if copies * elem_len > G:
+        raise ValueError("the copies do not fit the genome")
+    rng = np.random.default_rng(seed)
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    g = acgt[rng.integers(0, 4, G)]
+    elem = rng.integers(0, 4, elem_len)
+    for slot in np.sort(rng.choice(G // elem_len, copies, replace=False)):
+        c = elem.copy()
+        m = rng.random(elem_len) < div
+        c[m] = (c[m] + rng.integers(1, 4, int(m.sum()))) % 4
+        g[slot * elem_len:(slot + 1) * elem_len] = acgt[c]
+    return g
+
+
 def genome_repeats(G: int, seed: int, f_unique=0.5, f_segdup=0.4, f_tandem=0.1,
                    div_lo=0.01, div_hi=0.03, tandem_mut=0.01,
                    n_frac=0.0, n_run_lo=1000, n_run_hi=100000) -> np.ndarray:

@@ -88,6 +88,25 @@ def test_parameter_sweep(snapgpu, oracle_mod, synth_mod, c, hmax, dmax):
     _check(snapgpu, oracle_mod, w, g, reads, f"sweep c={c} h={hmax} d={dmax}", params=p)
 
 
+@pytest.mark.parametrize("copies", [1400, 5000])
+def test_high_copy_family(snapgpu, oracle_mod, synth_mod, copies):
+    """Reads from a high-copy repeat family: over 1024 and over 4096 candidate
+    locations per read, more than a heavy-replay wave stages in LDS (its reads
+    work in global memory), with hundreds of hits per seed."""
+    from dataclasses import replace
+    from synth.workloads import MID
+    G = 2_000_000 if copies < 3000 else 3_000_000
+    g = synth_mod.genome_family(G, 11, copies)
+    reads = synth_mod.simulate_reads(g, 1000, 12, MID.reads)
+    p = replace(MID.params, max_hits=2 * copies)
+    # the family's seeds hit most copies
+    oix = oracle_mod.Index(g, p.seed_len)
+    first = [oix.occ(bytes(reads.bases[reads.offsets[i]:reads.offsets[i] + 20])) or [] for i in range(reads.n)]
+    assert sum(len(o) > 0.5 * copies for o in first) > 50
+    _check(snapgpu, oracle_mod, MID, g, reads, f"family x{copies}", params=p, oix=oix)
+    oix.close()
+
+
 def test_long_reads_percent_dmax(snapgpu, oracle_mod, synth_mod):
     """Reads 100-700 bp with d_max = ceil(0.08 L) and the long-read error model."""
     from dataclasses import replace
