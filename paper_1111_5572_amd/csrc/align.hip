@@ -777,7 +777,9 @@ __device__ __forceinline__ int lv_lane_reg(const Stage &st, int L, int Tn, int K
                 int b = max(left, max(od, orr) + 2);
                 left = od;
                 b = min(b, lim2);
-                if (b >= max(0, -2 * d) && D > K) {
+                // diagonals after one that reached the end in this round are still
+                // extended (harmless: D stays e, and no later round runs)
+                if (b >= max(0, -2 * d)) {
                     nsteps++;
                     b = slide2<HAS_N>(st, b, 2 * d, lim2);
                     if (b >= L2) D = e;
@@ -914,9 +916,10 @@ struct WaveVerifyArgs {
                                 // cleared once verified
 };
 
-__device__ inline uint32_t lds_w16(const uint32_t *A, int i) {
-    const int w = i >> 4;
-    return funnel(A[w + 1], A[w], (uint32_t)(i & 15) * 2);
+// 16 bases of a staged array from bit offset b (base b / 2)
+__device__ inline uint32_t lds_b32(const uint32_t *A, int b) {
+    const int w = b >> 5;
+    return funnel(A[w + 1], A[w], (uint32_t)b);
 }
 
 // Extend diagonal d from read row i (text column i + d) while bases are equal, 16 per
@@ -929,23 +932,27 @@ struct WaveText {
     int L, Tn, strand;
 };
 
+// Rows in bit units as in the lane tile: from row b on diagonal d (d2 = 2d) up to
+// lim2 = 2 min(L, Tn - d), bases past the ends compared like any others and the
+// result cut back to lim2.
 template <bool HAS_N>
-__device__ inline int wave_slide(const WaveText &w, int i, int d) {
-    for (;;) {
-        const int j = i + d;
-        const int rem = min(w.L - i, w.Tn - j);
-        if (rem <= 0) return i;
-        const uint32_t x = lds_w16(w.RC, i) ^ lds_w16(w.TC, j);
-        uint32_t m = (x | (x >> 1)) & 0x55555555u;
-        if (HAS_N) {
-            const uint32_t rn = w.strand == 0 ? ext_mask16(w.rmask, w.xb + i)
-                                              : __builtin_bitreverse32(ext_mask16(w.rmask, w.xb + w.L - 16 - i)) >> 16;
-            m |= spread16(rn) | spread16(ext_mask16(w.gmask, w.p + j));
-        }
-        if (rem < 16) m |= 0xFFFFFFFFu << (2 * rem);
-        if (m == 0) { i += 16; continue; }
-        return i + (int)(__builtin_ctz(m) >> 1);
+__device__ inline int wave_slide2(const WaveText &w, int b, int d2, int lim2) {
+    if (b < lim2) {
+        uint32_t run;
+        do {
+            const uint32_t x = lds_b32(w.RC, b) ^ lds_b32(w.TC, b + d2);
+            uint32_t m = (x | (x >> 1)) & 0x55555555u;
+            if (HAS_N) {
+                const int i = b >> 1, j = (b + d2) >> 1;
+                const uint32_t rn = w.strand == 0 ? ext_mask16(w.rmask, w.xb + i)
+                                                  : __builtin_bitreverse32(ext_mask16(w.rmask, w.xb + w.L - 16 - i)) >> 16;
+                m |= spread16(rn) | spread16(ext_mask16(w.gmask, w.p + j));
+            }
+            run = m ? (uint32_t)__builtin_ctz(m) : 32u;
+            b += (int)run;
+        } while (run == 32u && b < lim2);
     }
+    return min(b, lim2);
 }
 
 // Furthest rows per diagonal for e = 0, 1, ..., K with lanes over diagonals (64 per
@@ -956,9 +963,10 @@ __device__ inline int lv_wave(const WaveText &w, int K, int16_t *F0, int16_t *F1
     constexpr int NEG = -30000;
     const int lane = threadIdx.x;
     const int L = w.L, Tn = w.Tn;
+    // rows are stored in bases (reads up to 16384 bases fit 16 bits), slid in bits
     for (int t = lane; t < 2 * max(K, 0) + 3; t += 64) { F0[t] = (int16_t)NEG; F1[t] = (int16_t)NEG; }
     int i0 = 0;
-    if (lane == 0) i0 = wave_slide<HAS_N>(w, 0, 0);
+    if (lane == 0) i0 = wave_slide2<HAS_N>(w, 0, 0, 2 * min(L, Tn)) >> 1;
     i0 = __shfl(i0, 0, 64);
     if (i0 >= L) return 0;
     if (lane == 0) F0[K + 1] = (int16_t)i0;
@@ -968,11 +976,12 @@ __device__ inline int lv_wave(const WaveText &w, int K, int16_t *F0, int16_t *F1
         bool hit = false;
         for (int d = -e + lane; d <= e; d += 64) {
             const int idx = d + K + 1;
+            const int lim = min(L, Tn - d);
             int i = max((int)prev[idx - 1], max((int)prev[idx], (int)prev[idx + 1]) + 1);
-            i = min(i, min(L, Tn - d));
+            i = min(i, lim);
             if (i >= max(0, -d)) {
                 nsteps++;
-                i = wave_slide<HAS_N>(w, i, d);
+                i = wave_slide2<HAS_N>(w, 2 * i, 2 * d, 2 * lim) >> 1;
                 if (i >= L) hit = true;
             } else {
                 i = NEG;
