@@ -41,11 +41,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+INDEX_ON_HOST = False   # --host-index
+
+
 def build_index(g, seed_len):
-    """Device index of the genome; logs each finished build stage (a large genome
-    takes minutes on the host)."""
+    """Device index of the genome, built by the library's device kernels (or, with
+    --host-index, on the host, logging each finished stage: minutes for a large genome)."""
     import paper_1111_5572_amd as snapgpu
     t0 = time.time()
+    if not INDEX_ON_HOST:
+        ix = snapgpu.Index(g, seed_len, on_device=True)
+        log(f"  index: built on the device ({time.time() - t0:.1f}s)")
+        return ix
     return snapgpu.Index(g, seed_len, progress=lambda stage: log(f"  index: {stage} ({time.time() - t0:.1f}s)"))
 
 
@@ -274,7 +281,8 @@ def bench_batched(args, w, dev):
                              "buckets": [list(b) for b in LENGTH_BUCKETS]},
         "speedup_vs_per_bucket": round(plain_s / batched_s, 3),
         "autotune": tune_info,
-        "index_build_s": round(index_s, 2), "index_device_bytes": sizes["device_bytes"],
+        "index_build_s": round(index_s, 2), "index_build": "host" if INDEX_ON_HOST else "device",
+        "index_device_bytes": sizes["device_bytes"],
         "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
         "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
@@ -418,6 +426,7 @@ def main():
                     help="counter summary giving the dominant kernel's HBM bytes per launch")
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule")
+    ap.add_argument("--host-index", action="store_true", help="build the index on the host (snap_index_build)")
     ap.add_argument("--retune", action="store_true",
                     help="run the autotuner even when the package's tuning table has this length class")
     ap.add_argument("--tuning", default="", help="fixed schedule a,b,c,d (snap_tuning fields); skips the autotuner")
@@ -425,6 +434,8 @@ def main():
                     help="only run the library's plain copy kernel over this many bytes, 3 times "
                          "(the known-size reference for HBM byte counters)")
     args = ap.parse_args()
+    global INDEX_ON_HOST
+    INDEX_ON_HOST = args.host_index
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -567,7 +578,8 @@ def main():
                    "seeds_per_read": w.params.n_min, "d_max": w.params.d_max, "conf_c": w.params.conf_c,
                    "max_hits": w.params.max_hits},
         "gbases_per_s": round(gbases_per_s, 4),
-        "index_build_s": round(index_s, 2), "index_device_bytes": sizes["device_bytes"],
+        "index_build_s": round(index_s, 2), "index_build": "host" if INDEX_ON_HOST else "device",
+        "index_device_bytes": sizes["device_bytes"],
         "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
         "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},

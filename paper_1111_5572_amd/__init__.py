@@ -122,6 +122,10 @@ def lib():
         L.snap_index_build.restype = ctypes.c_int
         L.snap_index_build_progress.argtypes = [P, u64, i32, PROGRESS_FN, P, ctypes.POINTER(P)]
         L.snap_index_build_progress.restype = ctypes.c_int
+        L.snap_index_build_device.argtypes = [P, u64, i32, P, ctypes.POINTER(P)]
+        L.snap_index_build_device.restype = ctypes.c_int
+        L.snap_debug_index_download.argtypes = [P, i32, P, u64]
+        L.snap_debug_index_download.restype = ctypes.c_int
         L.snap_index_free.argtypes = [P]
         L.snap_index_free.restype = ctypes.c_int
         L.snap_index_info.argtypes = [P, ctypes.POINTER(IndexSizes)]
@@ -210,13 +214,19 @@ PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_void_p)
 
 
 class Index:
-    """Device-resident seed index of a genome (snap_index_build). `progress`, if
-    given, is called with the text of each finished build stage."""
+    """Device-resident seed index of a genome: built on the host (snap_index_build;
+    `progress`, if given, is called with the text of each finished build stage) or, with
+    on_device=True, by device kernels on the current stream (snap_index_build_device)."""
 
-    def __init__(self, genome, seed_len: int = 20, progress=None):
+    def __init__(self, genome, seed_len: int = 20, progress=None, on_device: bool = False):
         g = _np_u8(genome)
         h = ctypes.c_void_p()
-        if progress is None:
+        if on_device:
+            import torch
+            stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+            _check(lib().snap_index_build_device(g.ctypes.data, g.shape[0], seed_len, stream, ctypes.byref(h)),
+                   "snap_index_build_device")
+        elif progress is None:
             _check(lib().snap_index_build(g.ctypes.data, g.shape[0], seed_len, ctypes.byref(h)), "snap_index_build")
         else:
             cb = PROGRESS_FN(lambda stage, ctx: progress(stage.decode()))
@@ -229,6 +239,21 @@ class Index:
     @property
     def handle(self):
         return self._h
+
+    def download(self, which: str) -> np.ndarray:
+        """A copy of one device array: "gcode", "gmask", "table" (slots x 2 uint64) or
+        "positions"."""
+        sz = self.sizes()
+        G = sz["genome_len"]
+        shape, dt, idx = {
+            "gcode": ((G + 15) // 16 + 4, np.uint32, 0),
+            "gmask": ((G + 31) // 32 + 4, np.uint32, 1),
+            "table": ((sz["table_slots"], 2), np.uint64, 2),
+            "positions": (sz["position_entries"], np.uint32, 3),
+        }[which]
+        out = np.empty(shape, dtype=dt)
+        _check(lib().snap_debug_index_download(self._h, idx, out.ctypes.data, out.nbytes), "snap_debug_index_download")
+        return out
 
     def sizes(self) -> dict:
         s = IndexSizes()
