@@ -91,12 +91,6 @@ int snap_index_build_progress(const uint8_t *genome, uint64_t len, int32_t seed_
  * or len >= 2^32), SNAP_ENOMEM, SNAP_EDEVICE. On error *out is NULL. */
 int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_len, void *stream, snap_index **out);
 
-/* Copy one device array of an index to host memory (for checks): which = 0 packed
- * genome (uint32 words), 1 N mask (uint32 words), 2 table (two uint64 per slot),
- * 3 positions (uint32). `bytes` must equal the array's size (from snap_index_info: G,
- * table_slots, position_entries). Synchronous. Errors: SNAP_EINVAL, SNAP_EDEVICE. */
-int snap_debug_index_download(const snap_index *ix, int32_t which, void *host_dst, uint64_t bytes);
-
 /* Release the index and its device memory. NULL is accepted. */
 int snap_index_free(snap_index *ix);
 

@@ -1,12 +1,14 @@
 /*
  * snapgpu test hooks: host-side evaluations of the library's own index layout
- * and seed order, for checking them without a GPU. Not part of the alignment
- * path; no device memory is touched.
+ * and seed order (checkable without a GPU), and copies of device memory for the
+ * GPU tests. Not part of the alignment path.
  */
 #ifndef SNAPGPU_DEBUG_H
 #define SNAPGPU_DEBUG_H
 
 #include <stdint.h>
+
+#include "snapgpu.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -37,6 +39,12 @@ int32_t snap_debug_seed_offsets(int32_t L, int32_t s, int32_t n, int32_t *out);
  * calibrating hardware byte counters. Returns SNAP_OK, SNAP_EINVAL, SNAP_EDEVICE.
  */
 int snap_debug_copy(const void *src, void *dst, uint64_t bytes, void *stream);
+
+/* Copy one device array of an index to host memory (for checks): which = 0 packed
+ * genome (uint32 words), 1 N mask (uint32 words), 2 table (two uint64 per slot),
+ * 3 positions (uint32). `bytes` must equal the array's size (from snap_index_info: G,
+ * table_slots, position_entries). Synchronous. Errors: SNAP_EINVAL, SNAP_EDEVICE. */
+int snap_debug_index_download(const snap_index *ix, int32_t which, void *host_dst, uint64_t bytes);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("index.hip", "index_gpu.hip", "align.hip", "server.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "snap_internal.h"), os.path.join(ROOT, "include", "snapgpu.h")]
+HEADERS = [os.path.join(HERE, "csrc", "snap_internal.h"), os.path.join(ROOT, "include", "snapgpu.h"),
+           os.path.join(ROOT, "include", "snapgpu_debug.h")]
 LIB = os.path.join(HERE, "libsnapgpu.so")
 
 HIPCC_FLAGS = [
@@ -25,11 +26,24 @@ def build(force: bool = True, verbose: bool = False) -> str:
         newest = max(os.path.getmtime(f) for f in SOURCES + HEADERS)
         if os.path.getmtime(LIB) >= newest:
             return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
+    # one object per source, compiled side by side, then one link
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    with tempfile.TemporaryDirectory(prefix="snapgpu_build_") as tdir:
+        objs = [os.path.join(tdir, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [["hipcc", *HIPCC_FLAGS, "-c", "-I", os.path.join(ROOT, "include"), "-o", obj, src]
+                for src, obj in zip(SOURCES, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c))
+        with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
+            for f in [ex.submit(subprocess.check_call, c) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp"
+        link = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(link))
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

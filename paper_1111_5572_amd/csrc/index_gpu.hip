@@ -28,6 +28,7 @@
 #include <rocprim/iterator/transform_iterator.hpp>
 
 #include "../../include/snapgpu.h"
+#include "../../include/snapgpu_debug.h"
 #include "snap_internal.h"
 
 using namespace snapgpu;
