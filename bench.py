@@ -49,11 +49,34 @@ def build_index(g, seed_len):
     --host-index, on the host, logging each finished stage: minutes for a large genome)."""
     import paper_1111_5572_amd as snapgpu
     t0 = time.time()
-    if not INDEX_ON_HOST:
-        ix = snapgpu.Index(g, seed_len, on_device=True)
-        log(f"  index: built on the device ({time.time() - t0:.1f}s)")
-        return ix
-    return snapgpu.Index(g, seed_len, progress=lambda stage: log(f"  index: {stage} ({time.time() - t0:.1f}s)"))
+    report = lambda stage: log(f"  index: {stage} ({time.time() - t0:.3f}s)")
+    return snapgpu.Index(g, seed_len, progress=report, on_device=not INDEX_ON_HOST)
+
+
+def bench_index(args, w):
+    """The index build alone: the workload's genome indexed --steps times (after one
+    untimed build); one JSON line with the mean build time (host-to-device copy of the
+    genome included)."""
+    import torch
+    g = w.make_genome()
+    log(f"genome {w.name}: {len(g)} bases")
+    times = []
+    for i in range(1 + max(1, args.steps)):
+        torch.cuda.synchronize()
+        t = time.time()
+        ix = build_index(g, w.params.seed_len)
+        torch.cuda.synchronize()
+        dt = time.time() - t
+        sizes = ix.sizes()
+        ix.close()
+        if i:
+            times.append(dt)
+        log(f"build {i}{' (untimed)' if i == 0 else ''}: {dt:.3f}s")
+    mean = sum(times) / len(times)
+    print(json.dumps({"metric": "index build", "value": round(mean, 4), "unit": "s", "higher_is_better": False,
+                      "n_gpus": 1, "steps": len(times), "index_build": "host" if INDEX_ON_HOST else "device",
+                      "config": {"workload": w.name, "genome_bases": len(g), "seed_len": w.params.seed_len},
+                      "sizes": sizes, "windows_per_s": round(sizes["windows"] / mean)}), flush=True)
 
 
 def roofline_of(kern, ctr, prefer=None):
@@ -427,6 +450,8 @@ def main():
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule")
     ap.add_argument("--host-index", action="store_true", help="build the index on the host (snap_index_build)")
+    ap.add_argument("--index-only", action="store_true",
+                    help="time the index build of the workload's genome (--steps builds) and stop")
     ap.add_argument("--retune", action="store_true",
                     help="run the autotuner even when the package's tuning table has this length class")
     ap.add_argument("--tuning", default="", help="fixed schedule a,b,c,d (snap_tuning fields); skips the autotuner")
@@ -460,6 +485,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.copy_bytes} bytes 3 times, equal: {bool(torch.equal(src, dst))}")
         return
+    if args.index_only:
+        return bench_index(args, w)
     if args.workload == "batched":
         return bench_batched(args, w, dev)
     if args.workload == "served":

@@ -82,14 +82,16 @@ int snap_index_build_progress(const uint8_t *genome, uint64_t len, int32_t seed_
  * omitted aspect 2): the genome (caller's host buffer, copied in and free to release on
  * return) is packed, every N-free window's records are radix-sorted by canonical code and
  * orientation and the table is filled by compare-and-swap, all by kernels on `stream`
- * (a hipStream_t; NULL = the default stream). Returns when the index is complete.
+ * (a hipStream_t; NULL = the default stream). Returns when the index is complete;
+ * `progress` (may be NULL) is told each finished stage, as for snap_index_build_progress.
  * The result answers every lookup exactly as snap_index_build's does: the same packed
  * genome, N mask and positions array and the same table entries, though an entry may sit
  * in another slot of its probe sequence. seed_len 1..31 (the sort key is the code and the
  * orientation bit). Device memory while sorting: about 24 bytes per window on top of the
  * index. Errors: SNAP_EINVAL (NULL genome or out, seed_len outside 1..31, len < seed_len
  * or len >= 2^32), SNAP_ENOMEM, SNAP_EDEVICE. On error *out is NULL. */
-int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_len, void *stream, snap_index **out);
+int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_len, void *stream,
+                            snap_progress_fn progress, void *ctx, snap_index **out);
 
 /* Release the index and its device memory. NULL is accepted. */
 int snap_index_free(snap_index *ix);

@@ -122,7 +122,7 @@ def lib():
         L.snap_index_build.restype = ctypes.c_int
         L.snap_index_build_progress.argtypes = [P, u64, i32, PROGRESS_FN, P, ctypes.POINTER(P)]
         L.snap_index_build_progress.restype = ctypes.c_int
-        L.snap_index_build_device.argtypes = [P, u64, i32, P, ctypes.POINTER(P)]
+        L.snap_index_build_device.argtypes = [P, u64, i32, P, PROGRESS_FN, P, ctypes.POINTER(P)]
         L.snap_index_build_device.restype = ctypes.c_int
         L.snap_debug_index_download.argtypes = [P, i32, P, u64]
         L.snap_debug_index_download.restype = ctypes.c_int
@@ -214,9 +214,9 @@ PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_void_p)
 
 
 class Index:
-    """Device-resident seed index of a genome: built on the host (snap_index_build;
-    `progress`, if given, is called with the text of each finished build stage) or, with
-    on_device=True, by device kernels on the current stream (snap_index_build_device)."""
+    """Device-resident seed index of a genome: built on the host (snap_index_build) or,
+    with on_device=True, by device kernels on the current stream (snap_index_build_device).
+    `progress`, if given, is called with the text of each finished build stage."""
 
     def __init__(self, genome, seed_len: int = 20, progress=None, on_device: bool = False):
         g = _np_u8(genome)
@@ -224,8 +224,9 @@ class Index:
         if on_device:
             import torch
             stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-            _check(lib().snap_index_build_device(g.ctypes.data, g.shape[0], seed_len, stream, ctypes.byref(h)),
-                   "snap_index_build_device")
+            cb = PROGRESS_FN(lambda stage, ctx: progress(stage.decode())) if progress else PROGRESS_FN()
+            _check(lib().snap_index_build_device(g.ctypes.data, g.shape[0], seed_len, stream, cb, None,
+                                                 ctypes.byref(h)), "snap_index_build_device")
         elif progress is None:
             _check(lib().snap_index_build(g.ctypes.data, g.shape[0], seed_len, ctypes.byref(h)), "snap_index_build")
         else:

@@ -49,21 +49,44 @@ __device__ inline uint32_t dev_base_code(uint8_t b) {
     }
 }
 
-// One thread per 32-base block: two code words and one N-mask word (N stored as 0).
-__global__ void k_pack_genome(const uint8_t *g, uint64_t G, uint32_t *gcode, uint32_t *gmask, int64_t nblk) {
-    const int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (blk >= nblk) return;
-    uint32_t c0 = 0, c1 = 0, m = 0;
-    for (int k = 0; k < 32; k++) {
-        const uint64_t j = (uint64_t)blk * 32 + k;
-        if (j >= G) break;
-        uint32_t c = dev_base_code(g[j]);
-        if (c > 3) { m |= 1u << k; c = 0; }
-        if (k < 16) c0 |= c << (2 * k); else c1 |= c << (2 * (k - 16));
+// One thread per 4 bases (one 32-bit load of the genome), 8 threads per 32-base block:
+// each contributes a byte of the two code words and 4 bits of the N-mask word, gathered
+// by shuffles (N stored as 0). Bases past G are none.
+__global__ __launch_bounds__(256) void k_pack_genome(const uint8_t *g, uint64_t G, uint32_t *gcode, uint32_t *gmask,
+                                                     int64_t nblk) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 4-base group
+    const int64_t blk = t >> 3;
+    const int part = (int)(t & 7);
+    uint32_t code = 0, m = 0;
+    if (blk < nblk) {
+        const uint64_t j0 = (uint64_t)t * 4;
+        uint32_t w = 0;
+        if (j0 + 4 <= G) {
+            w = *reinterpret_cast<const uint32_t *>(g + j0);   // the genome copy is 256-byte aligned
+        } else {
+            for (int k = 0; k < 4; k++) w |= (j0 + k < G ? (uint32_t)g[j0 + k] : (uint32_t)'A') << (8 * k);
+        }
+        for (int k = 0; k < 4; k++) {
+            uint32_t c = dev_base_code((uint8_t)(w >> (8 * k)));
+            const bool past = j0 + k >= G;
+            if (c > 3 && !past) m |= 1u << k;
+            if (c > 3 || past) c = 0;
+            code |= c << (2 * k);
+        }
     }
-    gcode[2 * blk] = c0;
-    gcode[2 * blk + 1] = c1;
-    gmask[blk] = m;
+    // gather the 8 parts of a block (lanes 8b .. 8b+7 of the wave)
+    const int lane = threadIdx.x & 63, b0 = lane & ~7;
+    uint32_t c0 = 0, c1 = 0, mm = 0;
+    for (int q = 0; q < 8; q++) {
+        const uint32_t cq = (uint32_t)__shfl((int)code, b0 + q, 64), mq = (uint32_t)__shfl((int)m, b0 + q, 64);
+        if (q < 4) c0 |= cq << (8 * q); else c1 |= cq << (8 * (q - 4));
+        mm |= mq << (4 * q);
+    }
+    if (blk < nblk && part == 0) {
+        gcode[2 * blk] = c0;
+        gcode[2 * blk + 1] = c1;
+        gmask[blk] = mm;
+    }
 }
 
 // Forward code of the s bases at q (first base least significant) and whether any is N.
@@ -91,15 +114,21 @@ __device__ inline uint32_t window_records(const uint32_t *gcode, const uint32_t 
     return (fw == canon ? 1u : 0u) | (rc == canon ? 2u : 0u);
 }
 
+// A block's 4096 windows: wave w of the block takes windows [1024 w, 1024 (w + 1)) of
+// it, 64 at a time, lane l the l-th (so a wave's loads and stores are contiguous).
+__device__ inline uint64_t emit_window(int k) {
+    return (uint64_t)blockIdx.x * EMIT_BLOCK + (uint64_t)(threadIdx.x >> 6) * (EMIT_WPT * 64) + (uint64_t)k * 64 +
+           (threadIdx.x & 63);
+}
+
 // Pass 1: per block, the records its windows give (low 32 bits) and its N-free windows
 // (high 32 bits).
 __global__ __launch_bounds__(EMIT_THREADS) void k_count_records(const uint32_t *gcode, const uint32_t *gmask,
                                                                 uint64_t nwin, int s, uint64_t *block_counts) {
-    const uint64_t q0 = (uint64_t)blockIdx.x * EMIT_BLOCK + (uint64_t)threadIdx.x * EMIT_WPT;
     uint32_t recs = 0, free_w = 0;
     for (int k = 0; k < EMIT_WPT; k++) {
         uint64_t canon = 0;
-        const uint32_t f = window_records(gcode, gmask, q0 + k, nwin, s, canon);
+        const uint32_t f = window_records(gcode, gmask, emit_window(k), nwin, s, canon);
         recs += (f & 1) + (f >> 1);
         free_w += f ? 1 : 0;
     }
@@ -118,35 +147,34 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_count_records(const uint32_t *
 }
 
 // Pass 2: the same windows write their records at the block's offset (exclusive scan
-// of the record counts), thread by thread in window order.
+// of the block counts) in window order: waves in order, and within a wave 64 windows at
+// a time, each lane's records placed after those of the lanes before it (ballots).
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit_records(const uint32_t *gcode, const uint32_t *gmask,
                                                                uint64_t nwin, int s, const uint64_t *block_off,
                                                                uint64_t *keys, uint32_t *vals) {
-    const uint64_t q0 = (uint64_t)blockIdx.x * EMIT_BLOCK + (uint64_t)threadIdx.x * EMIT_WPT;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t recs = 0;
     for (int k = 0; k < EMIT_WPT; k++) {
         uint64_t canon = 0;
-        const uint32_t f = window_records(gcode, gmask, q0 + k, nwin, s, canon);
+        const uint32_t f = window_records(gcode, gmask, emit_window(k), nwin, s, canon);
         recs += (f & 1) + (f >> 1);
     }
-    // exclusive scan of the threads' counts (Hillis-Steele in LDS)
-    __shared__ uint32_t sc[2][EMIT_THREADS];
-    int cur = 0;
-    sc[0][threadIdx.x] = recs;
+    for (int o = 32; o > 0; o >>= 1) recs += (uint32_t)__shfl_xor((int)recs, o, 64);
+    __shared__ uint32_t wave_recs[EMIT_THREADS / 64];
+    if (lane == 0) wave_recs[wv] = recs;
     __syncthreads();
-    for (int o = 1; o < EMIT_THREADS; o <<= 1) {
-        const uint32_t v = sc[cur][threadIdx.x] + ((int)threadIdx.x >= o ? sc[cur][threadIdx.x - o] : 0u);
-        sc[cur ^ 1][threadIdx.x] = v;
-        cur ^= 1;
-        __syncthreads();
-    }
-    uint64_t at = block_off[blockIdx.x] + (sc[cur][threadIdx.x] - recs);
+    uint64_t at = block_off[blockIdx.x];
+    for (int w = 0; w < wv; w++) at += wave_recs[w];
+    const uint64_t below = (1ull << lane) - 1;
     for (int k = 0; k < EMIT_WPT; k++) {
-        const uint64_t q = q0 + k;
+        const uint64_t q = emit_window(k);
         uint64_t canon = 0;
         const uint32_t f = window_records(gcode, gmask, q, nwin, s, canon);
-        if (f & 1) { keys[at] = canon << 1; vals[at] = (uint32_t)q; at++; }
-        if (f & 2) { keys[at] = (canon << 1) | 1; vals[at] = (uint32_t)q; at++; }
+        const uint64_t b0 = __ballot(f & 1), b1 = __ballot(f & 2);
+        uint64_t my = at + __popcll(b0 & below) + __popcll(b1 & below);
+        if (f & 1) { keys[my] = canon << 1; vals[my] = (uint32_t)q; my++; }
+        if (f & 2) { keys[my] = (canon << 1) | 1; vals[my] = (uint32_t)q; }
+        at += __popcll(b0) + __popcll(b1);
     }
 }
 
@@ -227,7 +255,16 @@ struct DevBuf {
 #define DEV_OK(x) do { if ((x) != hipSuccess) return SNAP_EDEVICE; } while (0)
 #define RC_OK(x) do { const int rc_ = (x); if (rc_ != SNAP_OK) return rc_; } while (0)
 
-int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, snap_index *ix) {
+// Stage reports of a build (stage text, null callback allowed).
+struct DevProgress {
+    snap_progress_fn fn;
+    void *ctx;
+    void operator()(const char *stage) const {
+        if (fn) fn(stage, ctx);
+    }
+};
+
+int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, const DevProgress &prog, snap_index *ix) {
     const uint64_t ncw = (G + 15) / 16 + GENOME_PAD_WORDS, nmw = (G + 31) / 32 + GENOME_PAD_WORDS;
     const int64_t nblk = (int64_t)((G + 31) / 32);
     DevBuf dg, gcode, gmask;
@@ -237,11 +274,12 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, snap_
     DEV_OK(hipMemcpyAsync(dg.p, genome, G, hipMemcpyHostToDevice, st));
     DEV_OK(hipMemsetAsync(gcode.p, 0, ncw * 4, st));
     DEV_OK(hipMemsetAsync(gmask.p, 0, nmw * 4, st));
-    hipLaunchKernelGGL(k_pack_genome, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, (const uint8_t *)dg.p, G,
-                       (uint32_t *)gcode.p, (uint32_t *)gmask.p, nblk);
+    hipLaunchKernelGGL(k_pack_genome, dim3((unsigned)((nblk * 8 + 255) / 256)), dim3(256), 0, st, (const uint8_t *)dg.p,
+                       G, (uint32_t *)gcode.p, (uint32_t *)gmask.p, nblk);
     DEV_OK(hipGetLastError());
     DEV_OK(hipStreamSynchronize(st));
     (void)hipFree(dg.release());
+    prog("copied the genome in and packed it");
     const uint32_t *gc = (const uint32_t *)gcode.p, *gm = (const uint32_t *)gmask.p;
 
     // records: count, scan, emit
@@ -288,7 +326,9 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, snap_
     hipLaunchKernelGGL(k_emit_records, dim3((unsigned)nb), dim3(EMIT_THREADS), 0, st, gc, gm, nwin, s,
                        (const uint64_t *)boff.p, (uint64_t *)k0.p, (uint32_t *)v0.p);
     DEV_OK(hipGetLastError());
+    DEV_OK(hipStreamSynchronize(st));
     (void)hipFree(boff.release());
+    prog("emitted the window records");
 
     // stable sort over the canonical code and orientation bits
     rocprim::double_buffer<uint64_t> kb((uint64_t *)k0.p, (uint64_t *)k1.p);
@@ -305,6 +345,7 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, snap_
     DevBuf *pos_buf = vb.current() == (uint32_t *)v0.p ? &v0 : &v1;
     (void)hipFree((keys_buf == &k0 ? k1 : k0).release());
     (void)hipFree((pos_buf == &v0 ? v1 : v0).release());
+    prog("sorted the records");
     const uint64_t *keys = (const uint64_t *)keys_buf->p;
 
     // distinct codes, table size as in the host build, then one insertion per run
@@ -333,6 +374,7 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, snap_
     DEV_OK(hipStreamSynchronize(st));
     if (failed) return SNAP_EDEVICE;
     (void)hipFree(keys_buf->release());
+    prog("filled the table");
 
     ix->d.G = G;
     ix->d.s = s;
@@ -356,7 +398,7 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, snap_
 }  // namespace
 
 extern "C" int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_len, void *stream,
-                                       snap_index **out) {
+                                       snap_progress_fn progress, void *ctx, snap_index **out) {
     if (!out) return SNAP_EINVAL;
     *out = nullptr;
     if (!genome || seed_len < 1 || seed_len > 31 || len < (uint64_t)seed_len || len >= (1ull << 32))
@@ -364,7 +406,7 @@ extern "C" int snap_index_build_device(const uint8_t *genome, uint64_t len, int3
     snap_index *ix = new (std::nothrow) snap_index();
     if (!ix) return SNAP_ENOMEM;
     if (hipGetDevice(&ix->device) != hipSuccess) { delete ix; return SNAP_EDEVICE; }
-    const int rc = build_device(genome, len, seed_len, (hipStream_t)stream, ix);
+    const int rc = build_device(genome, len, seed_len, (hipStream_t)stream, DevProgress{progress, ctx}, ix);
     if (rc != SNAP_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         snap_index_free(ix);
