@@ -53,6 +53,73 @@ def build_index(g, seed_len):
     return snapgpu.Index(g, seed_len, progress=report, on_device=not INDEX_ON_HOST)
 
 
+HMAX_SWEEP = (10, 25, 50, 100, 200, 300, 500, 1000, 2000)
+
+
+def accuracy_of(out, reads, tol=32):
+    """The paper's Section 2 metrics for simulated reads: aligned = share of reads given a
+    single (confident) location; errors = share of those whose strand differs from the
+    read's source or whose position is more than `tol` bases from it."""
+    pos, strand, _, _, call = out
+    single = call == 1
+    wrong = single & ((strand != reads.truth_strand) | (np.abs(pos - reads.truth_pos) > tol))
+    n_single = int(single.sum())
+    return {"aligned_pct": round(100.0 * n_single / max(reads.n, 1), 3),
+            "error_pct": round(100.0 * int(wrong.sum()) / max(n_single, 1), 4)}
+
+
+def bench_accuracy(args, w, dev):
+    """The h_max trade-off (Section 4's figure on h_max: more candidate locations per seed
+    align more reads with fewer errors, at lower throughput): 125 bp reads with a 2% error
+    rate (1.8% substitutions, 0.2% indels of 1-5 bases) on the workload's genome, d_max 8,
+    aligned and error rates against the reads' source and reads/s for each h_max."""
+    import torch
+    import synth
+    import paper_1111_5572_amd as snapgpu
+    from dataclasses import replace
+    g = w.make_genome()
+    model = synth.ReadModel(len_mode=0, len_a=125, len_b=125, p_sub=0.018, p_indel=0.002, indel_max=5)
+    n = args.reads or 1_000_000
+    t = time.time()
+    reads = synth.simulate_reads(g, n, 105, model)
+    log(f"genome {w.name}: {len(g)} bases; {n} reads of 125 bp in {time.time() - t:.1f}s")
+    gix = build_index(g, w.params.seed_len)
+    rb = torch.from_numpy(reads.bases).to(dev)
+    ln = torch.from_numpy(reads.lengths).to(dev)
+    from paper_1111_5572_amd import autotune
+    tuning = autotune.lookup(reads.lengths, batched=False)
+    if tuning:
+        snapgpu.set_tuning(*tuning)
+    log(f"schedule {tuning or 'library default'}")
+    stream = torch.cuda.current_stream()
+    rows = []
+    out = None
+    for h in HMAX_SWEEP:
+        p = snapgpu.params_from(replace(w.params, max_hits=h, d_max=8))
+        out = snapgpu.align(gix, rb, ln, 8, p, out=out, max_len=125)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(max(1, args.steps)):
+            out = snapgpu.align(gix, rb, ln, 8, p, out=out, max_len=125)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / max(1, args.steps)
+        row = {"h_max": h, **accuracy_of(out.numpy(), reads), "reads_per_s": round(n / (ms / 1e3), 1),
+               "ms_per_step": round(ms, 3)}
+        log(f"h_max {h}: {row}")
+        rows.append(row)
+    gix.close()
+    print(json.dumps({"metric": "h_max trade-off", "unit": "aligned %, error %, reads/s", "n_gpus": 1,
+                      "steps": max(1, args.steps), "data": "synthetic (seeded genome and simulated reads)",
+                      "config": {"workload": w.name, "genome_bases": len(g), "reads": n, "read_len": 125,
+                                 "errors": "1.8% substitutions, 0.2% indels (1-5)", "d_max": 8,
+                                 "conf_c": w.params.conf_c, "seed_len": w.params.seed_len,
+                                 "correct": "same strand, |pos - source| <= 32",
+                                 "schedule": list(tuning) if tuning else None},
+                      "rows": rows}), flush=True)
+
+
 def bench_index(args, w):
     """The index build alone: the workload's genome indexed --steps times (after one
     untimed build); one JSON line with the mean build time (host-to-device copy of the
@@ -450,6 +517,8 @@ def main():
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule")
     ap.add_argument("--host-index", action="store_true", help="build the index on the host (snap_index_build)")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="h_max sweep: aligned / error rates and reads/s for 125 bp reads at 2%% errors")
     ap.add_argument("--index-only", action="store_true",
                     help="time the index build of the workload's genome (--steps builds) and stop")
     ap.add_argument("--retune", action="store_true",
@@ -487,6 +556,8 @@ def main():
         return
     if args.index_only:
         return bench_index(args, w)
+    if args.accuracy:
+        return bench_accuracy(args, w, dev)
     if args.workload == "batched":
         return bench_batched(args, w, dev)
     if args.workload == "served":

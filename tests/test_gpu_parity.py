@@ -79,7 +79,8 @@ def test_human_recipe_scaled_with_n(snapgpu, oracle_mod, synth_mod):
     _check(snapgpu, oracle_mod, w, g, reads, "human-scaled")
 
 
-@pytest.mark.parametrize("c,hmax,dmax", [(1, 300, 10), (3, 300, 10), (2, 8, 10), (2, 60, 4), (2, 300, 0)])
+@pytest.mark.parametrize("c,hmax,dmax", [(1, 300, 10), (3, 300, 10), (2, 8, 10), (2, 60, 4), (2, 300, 0),
+                                         (2, 2000, 8)])
 def test_parameter_sweep(snapgpu, oracle_mod, synth_mod, c, hmax, dmax):
     from dataclasses import replace
     from synth.workloads import MID
