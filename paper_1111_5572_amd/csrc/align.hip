@@ -253,18 +253,35 @@ struct ProbeArgs {
     ProbeRec *out;         // nr * NS records
 };
 
-// Eight lanes per (read, seed slot): each lane reads one 16-byte slot of the
-// seed's 128-byte bucket, so one probe is one coalesced cache-line read.
+// A wave takes 64 (read, seed slot) items. First each lane computes one item's seed
+// (offset, 2s-bit code, N test, canonical code); then in 8 rounds every group of eight
+// lanes probes one item, each lane reading one 16-byte slot of the seed's 128-byte
+// bucket (one coalesced cache line per probe step); results come back to the item's
+// lane through LDS, and each lane writes its own record.
 __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t item = gt >> 3;
-    const int sub = (int)(gt & 7);
-    const int lane = threadIdx.x & 63;
+    __shared__ uint64_t res_val[4][64];
+    __shared__ uint8_t res_found[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int sub = lane & 7, grp = lane >> 3;
     const int s = a.ix.s;
     const int NS = a.ps.NS;
-    const bool valid = item < a.ps.nr * (int64_t)NS;
-    const int64_t r = valid ? item / NS : 0;
-    const int i = valid ? (int)(item % NS) : 0;
+    const int64_t nitems = a.ps.nr * (int64_t)NS;
+    const int64_t item = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64 + lane;
+    const bool valid = item < nitems;
+    // item = r * NS + i (32-bit division when the pass's items fit 32 bits, as they do
+    // for any chunk of up to 2^27 reads)
+    int64_t r = 0;
+    int i = 0;
+    if (valid) {
+        if (nitems <= 0xFFFFFFFFll) {
+            const uint32_t r32 = (uint32_t)item / (uint32_t)NS;
+            r = r32;
+            i = (int)((uint32_t)item - r32 * (uint32_t)NS);
+        } else {
+            r = item / NS;
+            i = (int)(item - r * NS);
+        }
+    }
     const int64_t g = valid ? gid(a.ps, r) : 0;
     const int L = valid ? a.len[g] : 0;
     int o = -1;
@@ -289,42 +306,58 @@ __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
             canon = key < rc ? key : rc;
         }
     }
-    bool pending = (status == ST_OK);
-    uint64_t b = pending ? home_bucket(canon, a.ix.log2_buckets) : 0;
-    uint64_t val = 0;
-    bool found = false, writer = (sub == 0) && !pending;
-    uint64_t steps = 0;
-    // every group runs until its probe ends; the loop is uniform over the wave.
-    // The table is at most 70% full, so an empty slot ends every probe; the step
-    // bound only guarantees termination on a corrupted table.
-    for (;;) {
-        uint64_t k0 = EMPTY_KEY, v0 = 0;
-        if (pending) {
-            const uint64_t slot = b * SLOTS_PER_BUCKET + sub;
-            const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(a.ix.table + 2 * slot);
-            k0 = e.x;
-            v0 = e.y;
-        }
-        const uint64_t hit = __ballot(pending && k0 == canon);
-        const uint64_t emp = __ballot(pending && k0 == EMPTY_KEY);
-        const int g0 = lane & ~7;
-        const uint32_t ghit = (uint32_t)(hit >> g0) & 0xFFu, gemp = (uint32_t)(emp >> g0) & 0xFFu;
-        if (pending) {
-            if (ghit) {
-                // the lane holding the key writes the record
-                if (sub == __builtin_ctz(ghit)) { found = true; val = v0; writer = true; }
-                pending = false;
-            } else if (gemp) {
-                writer = (sub == 0);
-                pending = false;
-            } else {
-                b = (b + 1) & (a.ix.nbuckets - 1);
-                if (++steps >= a.ix.nbuckets) { writer = (sub == 0); pending = false; }
+    const int g0 = lane & ~7;
+    for (int j = 0; j < 8; j++) {
+        // group grp probes the item of lane src
+        const int src = j * 8 + grp;
+        const bool ok = __shfl(status, src, 64) == ST_OK;
+        const uint32_t clo = (uint32_t)__shfl((int)(uint32_t)canon, src, 64);
+        const uint32_t chi = (uint32_t)__shfl((int)(uint32_t)(canon >> 32), src, 64);
+        const uint64_t ckey = ((uint64_t)chi << 32) | clo;
+        bool pending = ok;
+        uint64_t b = pending ? home_bucket(ckey, a.ix.log2_buckets) : 0;
+        uint64_t steps = 0;
+        bool found = false;
+        uint64_t val = 0;
+        // every group runs until its probe ends; the loop is uniform over the wave.
+        // The table is at most 70% full, so an empty slot ends every probe; the step
+        // bound only guarantees termination on a corrupted table.
+        for (;;) {
+            uint64_t k0 = EMPTY_KEY, v0 = 0;
+            if (pending) {
+                const uint64_t slot = b * SLOTS_PER_BUCKET + sub;
+                const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(a.ix.table + 2 * slot);
+                k0 = e.x;
+                v0 = e.y;
             }
+            const uint64_t hit = __ballot(pending && k0 == ckey);
+            const uint64_t emp = __ballot(pending && k0 == EMPTY_KEY);
+            const uint32_t ghit = (uint32_t)(hit >> g0) & 0xFFu, gemp = (uint32_t)(emp >> g0) & 0xFFu;
+            if (pending) {
+                if (ghit) {
+                    if (sub == __builtin_ctz(ghit)) { found = true; val = v0; }
+                    pending = false;
+                } else if (gemp) {
+                    pending = false;
+                } else {
+                    b = (b + 1) & (a.ix.nbuckets - 1);
+                    if (++steps >= a.ix.nbuckets) pending = false;
+                }
+            }
+            if (__ballot(pending) == 0) break;
         }
-        if (__ballot(pending) == 0) break;
+        // the lane that found the key reports it; sub 0 clears the flag first
+        if (sub == 0) res_found[wv][src] = 0;
+        __builtin_amdgcn_wave_barrier();
+        if (found) {
+            res_val[wv][src] = val;
+            res_found[wv][src] = 1;
+        }
     }
-    if (!valid || !writer) return;
+    __builtin_amdgcn_wave_barrier();
+    if (!valid) return;
+    const bool found = res_found[wv][lane] != 0;
+    const uint64_t val = res_val[wv][lane];
     ProbeRec rec{};
     rec.status = (uint8_t)status;
     rec.o = (uint16_t)(o < 0 ? 0 : o);
@@ -2346,7 +2379,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             int64_t nr = std::min<int64_t>(R, b0 - r0);
             Pass ps{ridx, r0, nr, NSp, Kcap, final_pass};
             ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, ps, rule, sh, probe};
-            const int64_t pthreads = nr * NSp * 8;
+            const int64_t pthreads = nr * NSp;   // one lane per (read, seed slot)
             timed("probe", st, [&] { hipLaunchKernelGGL(k_probe, dim3((unsigned)((pthreads + 255) / 256)), dim3(256), 0, st, pa); });
             timed("hitcount", st, [&] { hipLaunchKernelGGL(k_hitcount, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, probe, nr, NSp, hits); });
             size_t tb = scan_tmp_bytes(nr + 1);
