@@ -251,13 +251,16 @@ struct ProbeArgs {
     Rule rule;
     Shifts sh;
     ProbeRec *out;         // nr * NS records
+    uint32_t *hits;        // per read: hits of its looked-up seeds (zeroed before the launch)
 };
 
 // A wave takes 64 (read, seed slot) items. First each lane computes one item's seed
 // (offset, 2s-bit code, N test, canonical code); then in 8 rounds every group of eight
 // lanes probes one item, each lane reading one 16-byte slot of the seed's 128-byte
 // bucket (one coalesced cache line per probe step); results come back to the item's
-// lane through LDS, and each lane writes its own record.
+// lane through LDS, and each lane writes its own record. A read's hits (the counts of
+// its looked-up seeds within h_max) are summed over its lanes by a segmented scan; a
+// read split between two waves adds its two parts atomically.
 __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
     __shared__ uint64_t res_val[4][64];
     __shared__ uint8_t res_found[4][64];
@@ -355,8 +358,7 @@ __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (!valid) return;
-    const bool found = res_found[wv][lane] != 0;
+    const bool found = valid && res_found[wv][lane] != 0;
     const uint64_t val = res_val[wv][lane];
     ProbeRec rec{};
     rec.status = (uint8_t)status;
@@ -372,21 +374,24 @@ __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
             rec.off_f = off + nf; rec.nf = nrv; rec.off_r = off; rec.nr = nf;
         }
     }
-    a.out[item] = rec;
+    if (valid) a.out[item] = rec;
+    // per-read hit sums
+    const uint32_t rkey = valid ? (uint32_t)r : 0xFFFFFFFFu;
+    uint32_t cnt = (valid && rec.status == ST_OK) ? rec.nf + rec.nr : 0u, len = valid ? 1u : 0u;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t c2 = (uint32_t)__shfl_up((int)cnt, d, 64), l2 = (uint32_t)__shfl_up((int)len, d, 64);
+        const uint32_t k2 = (uint32_t)__shfl_up((int)rkey, d, 64);
+        if (lane >= d && k2 == rkey) { cnt += c2; len += l2; }
+    }
+    const uint32_t knext = (uint32_t)__shfl_down((int)rkey, 1, 64);
+    if (valid && (lane == 63 || knext != rkey)) {
+        if (len == (uint32_t)NS) a.hits[r] = cnt;
+        else atomicAdd(&a.hits[r], cnt);
+    }
 }
 
 // ------------------------------------------------------------ candidates
 
-__global__ void k_hitcount(const ProbeRec *pr, int64_t nr, int NS, uint32_t *hits) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    uint32_t h = 0;
-    for (int i = 0; i < NS; i++) {
-        const ProbeRec &p = pr[r * NS + i];
-        if (p.status == ST_OK) h += p.nf + p.nr;
-    }
-    hits[r] = h;
-}
 
 constexpr uint64_t HIT_NONE = ~0ull;
 
@@ -2378,10 +2383,10 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
           for (int64_t r0 = a0; r0 < b0;) {
             int64_t nr = std::min<int64_t>(R, b0 - r0);
             Pass ps{ridx, r0, nr, NSp, Kcap, final_pass};
-            ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, ps, rule, sh, probe};
+            ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, ps, rule, sh, probe, hits};
             const int64_t pthreads = nr * NSp;   // one lane per (read, seed slot)
+            hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, hits, nr, 0u);
             timed("probe", st, [&] { hipLaunchKernelGGL(k_probe, dim3((unsigned)((pthreads + 255) / 256)), dim3(256), 0, st, pa); });
-            timed("hitcount", st, [&] { hipLaunchKernelGGL(k_hitcount, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, probe, nr, NSp, hits); });
             size_t tb = scan_tmp_bytes(nr + 1);
             HIP_OK(scan_excl(scan_tmp, tb, CastU32{hits, nr}, nr + 1, hoff, st));
             // total hits, the largest per-read count and the reads of the two sorting
