@@ -406,23 +406,36 @@ struct GatherArgs {
     uint64_t *hk;      // per hit: ((p << 1 | strand) << 5) | seed slot, or HIT_NONE
 };
 
-// Algorithm 1's vote loop, one wave per read. Lane i holds seed slot i's probe
-// record; a wave prefix sum places each slot's hits in the read's region; the lanes
-// then take 64 hits at a time (coalesced position reads and hit writes). A forward
-// hit q of the seed at offset o votes for (+, q - o), a reverse hit for
-// (-, q - (L - o - s)); locations outside [0, G - L] are dropped.
+// Algorithm 1's vote loop. A wave takes 64 / NS whole reads at a time, lane k holding
+// seed slot k of them (the reads' hit regions are then one contiguous range of the hit
+// array). A wave prefix sum of the slots' hit counts places every slot's hits, slot
+// by slot and forward before reverse within a slot; then the lanes take 64 hits of the
+// range at a time (coalesced position reads and hit writes), each finding its slot by
+// a binary search over the slots' starts in LDS. A forward hit q of the seed at offset
+// o votes for (+, q - o), a reverse hit for (-, q - (L - o - s)); locations outside
+// [0, G - L] are dropped.
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
+    __shared__ uint32_t s_start[4][64];
+    __shared__ uint32_t s_nf[4][64];
+    __shared__ uint64_t s_offf[4][64], s_offr[4][64];
+    __shared__ int32_t s_ofs[4][64], s_len[4][64];
     const int NS = a.ps.NS;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r = wave; r < a.ps.nr; r += nwaves) {
-        const int64_t base = a.hoff[r];
-        const int64_t L = a.len[gid(a.ps, r)];
-        uint32_t cnt = 0, nf = 0, o = 0;
+    const int rpw = 64 / NS;                       // reads per wave step
+    const int nitems = rpw * NS;
+    for (int64_t r0 = wave * rpw; r0 < a.ps.nr; r0 += nwaves * rpw) {
+        const int nrd = (int)min((int64_t)rpw, a.ps.nr - r0);
+        const int rl = lane / NS, i = lane - rl * NS;
+        const bool mine = lane < nrd * NS;
+        const int64_t r = r0 + rl;
+        uint32_t cnt = 0, nf = 0;
         uint64_t offf = 0, offr = 0;
-        if (lane < NS) {
-            const ProbeRec p = a.pr[r * NS + lane];
+        int o = 0, L = 0;
+        if (mine) {
+            const ProbeRec p = a.pr[r * NS + i];
+            L = a.len[gid(a.ps, r)];
             if (p.status == ST_OK) {
                 cnt = p.nf + p.nr;
                 nf = p.nf;
@@ -433,38 +446,45 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
         }
         uint32_t incl = cnt;
         for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t v = __shfl_up(incl, d, 64);
+            const uint32_t v = (uint32_t)__shfl_up((int)incl, d, 64);
             if (lane >= d) incl += v;
         }
-        const uint32_t start = incl - cnt;
-        const uint32_t H = __shfl(incl, 63, 64);
-        // chunks of 64 hits, every lane taking part in the shuffles (a shuffle reads
-        // nothing useful from a lane that is switched off)
-        for (uint32_t j0 = 0; j0 < H; j0 += 64) {
-            const uint32_t j = j0 + lane;
-            // the slot whose range holds hit j
-            int slot = 0;
-            for (int i = 1; i < NS; i++) {
-                const uint32_t si = __shfl(start, i, 64), ci = __shfl(cnt, i, 64);
-                if (si <= j && ci > 0) slot = i;
-            }
-            const uint32_t k = j - __shfl(start, slot, 64);
-            const uint32_t snf = __shfl(nf, slot, 64);
-            const int64_t so = __shfl(o, slot, 64);
-            const uint64_t offF = ((uint64_t)__shfl((uint32_t)(offf >> 32), slot, 64) << 32) | __shfl((uint32_t)offf, slot, 64);
-            const uint64_t offR = ((uint64_t)__shfl((uint32_t)(offr >> 32), slot, 64) << 32) | __shfl((uint32_t)offr, slot, 64);
-            if (j < H) {
-                uint64_t h;
-                if (k < snf) {
-                    const int64_t pp = (int64_t)a.positions[offF + k] - so;
-                    h = (pp >= 0 && pp + L <= (int64_t)a.G) ? (((uint64_t)pp << 1) << 5) | (uint64_t)slot : HIT_NONE;
-                } else {
-                    const int64_t pp = (int64_t)a.positions[offR + (k - snf)] - (L - so - a.s);
-                    h = (pp >= 0 && pp + L <= (int64_t)a.G) ? ((((uint64_t)pp << 1) | 1) << 5) | (uint64_t)slot : HIT_NONE;
+        const uint32_t H = (uint32_t)__shfl((int)incl, 63, 64);
+        if (lane < nitems) {
+            s_start[wv][lane] = incl - cnt;
+            s_nf[wv][lane] = nf;
+            s_offf[wv][lane] = offf;
+            s_offr[wv][lane] = offr;
+            s_ofs[wv][lane] = o;
+            s_len[wv][lane] = L;
+        }
+        const int64_t base = a.hoff[r0];
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t h0 = 0; h0 < H; h0 += 64) {
+            const uint32_t h = h0 + lane;
+            if (h < H) {
+                // the last slot whose start is at most h (it holds h: the next start is above it)
+                int lo = 0, hi = nitems - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_start[wv][mid] <= h) lo = mid; else hi = mid - 1;
                 }
-                a.hk[base + j] = h;
+                const uint32_t k = h - s_start[wv][lo];
+                const uint32_t snf = s_nf[wv][lo];
+                const int64_t so = s_ofs[wv][lo], sl = s_len[wv][lo];
+                const uint64_t slot = (uint64_t)(lo % NS);
+                uint64_t hv;
+                if (k < snf) {
+                    const int64_t pp = (int64_t)a.positions[s_offf[wv][lo] + k] - so;
+                    hv = (pp >= 0 && pp + sl <= (int64_t)a.G) ? (((uint64_t)pp << 1) << 5) | slot : HIT_NONE;
+                } else {
+                    const int64_t pp = (int64_t)a.positions[s_offr[wv][lo] + (k - snf)] - (sl - so - a.s);
+                    hv = (pp >= 0 && pp + sl <= (int64_t)a.G) ? ((((uint64_t)pp << 1) | 1) << 5) | slot : HIT_NONE;
+                }
+                a.hk[base + h] = hv;
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -2418,7 +2438,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             }
             if (total > 0) {
                 GatherArgs ga{probe, ix->d.positions, ix->d.G, ix->d.s, lengths, ps, hoff, hk};
-                const unsigned gb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
+                const int64_t rpb = 4 * (64 / NSp);   // reads per block step (4 waves)
+                const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + rpb - 1) / rpb, 8192));
                 timed("gather", st, [&] { hipLaunchKernelGGL(k_gather, dim3(gb), dim3(256), 0, st, ga); });
             }
             DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, slot_read, nullptr, nullptr};
