@@ -631,20 +631,22 @@ __global__ __launch_bounds__(NT) void k_dedupe_heavy(DedupeArgs a, uint64_t *gsc
             a.slot_read[base + i] = (uint32_t)r;
         }
         __syncthreads();
-        for (uint32_t k = 2; k <= N; k <<= 1) {
-            const uint32_t half = k >> 1;
+        // k, half and j are powers of two: indices by shifts and masks
+        for (uint32_t lk = 1; (1u << lk) <= N; lk++) {
+            const uint32_t k = 1u << lk, lh = lk - 1, half = k >> 1;
             for (uint32_t i = tid; i < N / 2; i += NT) {
-                const uint32_t blk = i / half, off = i % half;
-                const uint32_t lo = blk * k + off, hi = blk * k + k - 1 - off;
+                const uint32_t blk = i >> lh, off = i & (half - 1);
+                const uint32_t lo = (blk << lk) + off, hi = (blk << lk) + k - 1 - off;
                 if (hi < H) {
                     const uint64_t x = sk[lo], y = sk[hi];
                     if (y < x) { sk[lo] = y; sk[hi] = x; }
                 }
             }
             __syncthreads();
-            for (uint32_t j = k >> 2; j > 0; j >>= 1) {
+            for (int lj = (int)lk - 2; lj >= 0; lj--) {
+                const uint32_t j = 1u << lj;
                 for (uint32_t i = tid; i < N / 2; i += NT) {
-                    const uint32_t lo = (i / j) * 2 * j + (i % j), hi = lo + j;
+                    const uint32_t lo = ((i >> lj) << (lj + 1)) + (i & (j - 1)), hi = lo + j;
                     if (hi < H) {
                         const uint64_t x = sk[lo], y = sk[hi];
                         if (y < x) { sk[lo] = y; sk[hi] = x; }
