@@ -921,7 +921,7 @@ __device__ __forceinline__ void verify_lane(const VerifyArgs &a, int64_t k, uint
 
     uint32_t nsteps = 1;
     int D;
-    if constexpr (KMAX <= 7)
+    if constexpr (KMAX <= 11)
         D = anyn ? lv_lane_reg<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane_reg<KMAX, false>(st, L, Tn, K, nsteps);
     else
         D = anyn ? lv_lane<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane<KMAX, false>(st, L, Tn, K, nsteps);
@@ -2587,8 +2587,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     hipLaunchKernelGGL(k_flatten_requests, dim3(fb), dim3(256), 0, st, qa, req_off, long_list);
                     const int kfull = std::min(Kmax, LANE_KMAX);
                     const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
-                    const int kmf = kfull <= 7 ? 7 : (kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63));
-                    const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 7 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
+                    // requested limits up to 11 keep their rows in registers too
+                    const int kmf = kfull <= 7 ? 7 : (kfull <= 11 ? 11 : (kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63)));
+                    const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 11 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
                     VerifyArgs vq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
                                   coff + nr, rule, RW, TWf, dcap, vlim, steps, long_list, req_off + nrep, rq};
                     // as many waves as fit the device (the count is on the device)
@@ -2596,6 +2597,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     timed("verify_request", st, [&] {
                         if (kmf == 7)
                             hipLaunchKernelGGL(k_verify_requested<7>, dim3(vb), dim3(64), ldsf, st, vq);
+                        else if (kmf == 11)
+                            hipLaunchKernelGGL(k_verify_requested<11>, dim3(vb), dim3(64), ldsf, st, vq);
                         else if (kmf == 15)
                             hipLaunchKernelGGL(k_verify_requested<15>, dim3(vb), dim3(64), ldsf, st, vq);
                         else if (kmf == 31)
