@@ -2592,8 +2592,10 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 11 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
                     VerifyArgs vq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
                                   coff + nr, rule, RW, TWf, dcap, vlim, steps, long_list, req_off + nrep, rq};
-                    // as many waves as fit the device (the count is on the device)
-                    const unsigned vb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)cus * 16));
+                    // as many waves as fit the device (the count is on the device): rows in
+                    // registers leave room for 24 a CU, rows in LDS for 16
+                    const int64_t per_cu = kmf <= 11 ? 24 : 16;
+                    const unsigned vb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)cus * per_cu));
                     timed("verify_request", st, [&] {
                         if (kmf == 7)
                             hipLaunchKernelGGL(k_verify_requested<7>, dim3(vb), dim3(64), ldsf, st, vq);
