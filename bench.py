@@ -164,11 +164,17 @@ def roofline_of(kern, ctr, prefer=None):
         bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
         work = (ctr["hits"] * DEDUPE_BYTES_PER_HIT + ctr["locations"] * DEDUPE_BYTES_PER_LOC) * per_launch / 1e9
     elif dom.startswith("verify"):
-        # every verify kernel of the step shares the step counter; split it by time
-        vt = sum(v[1] for k, v in kern.items() if k.startswith("verify"))
-        share = total_ms / vt if vt > 0 else 1.0
+        # the first verification's diagonal extensions are counted on their own; the
+        # kernels that verify requested locations share the rest, split by their time
         bound, unit, peak = "alu", "TOP/s", VALU_PEAK_TOPS
-        work = ctr["lv_steps"] * share * VERIFY_OPS_PER_STEP * per_launch / 1e12
+        first = ctr.get("lv_steps_first", 0)
+        if dom in ("verify", "verify_steal"):
+            steps = first
+        else:
+            req = [k for k in kern if k.startswith("verify") and k not in ("verify", "verify_steal")]
+            vt = sum(kern[k][1] for k in req)
+            steps = (ctr["lv_steps"] - first) * (total_ms / vt if vt > 0 else 1.0)
+        work = steps * VERIFY_OPS_PER_STEP * per_launch / 1e12
     else:
         bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
         work = float("nan")

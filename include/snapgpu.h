@@ -319,6 +319,8 @@ typedef struct {
     int64_t second_pass_reads; /* reads a first pass left to a later pass */
     int64_t requests;     /* replays of reads after the verification they asked for */
     int64_t workers;      /* most chunk workers (host thread + stream) one call used */
+    int64_t lv_steps_first; /* of lv_steps, those of the first verification of every location
+                             * (the rest verified what replays asked for) */
 } snap_counters;
 
 int snap_profile_counters(snap_counters *out);

@@ -105,7 +105,7 @@ class ServerStats(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "second_pass_reads", "requests",
-                 "workers")]
+                 "workers", "lv_steps_first")]
 
 
 def lib():

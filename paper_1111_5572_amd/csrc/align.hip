@@ -2393,6 +2393,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         uint32_t *short_list = W.short_list, *long_list = W.long_list;
         int16_t *rq = W.rq;
         unsigned long long *steps_sum = (unsigned long long *)(misc + 6);
+        unsigned long long *steps_first = (unsigned long long *)(misc + 7);
         int64_t *sel_n = misc + 20;   // selected counts: [2] reads to replay, [3] reads for the next pass, ...
         unsigned long long *route_cnt = (unsigned long long *)(misc + 8);   // two counters
         unsigned long long *steal_next = (unsigned long long *)(misc + 10);  // two cursors
@@ -2542,6 +2543,12 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                             hipLaunchKernelGGL(k_verify<63>, dim3(vb), dim3(64), lds, st, va);
                     });
                 }
+                if (g_prof_on) {
+                    // profiling: the first verification's own diagonal extensions, before
+                    // requests add theirs to the same per-location counts
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)steps_first, 2, 0u);
+                    hipLaunchKernelGGL(k_sum_u32, dim3(256), dim3(256), 0, st, steps, coff + nr, steps_first);
+                }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
                           rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax,
@@ -2647,12 +2654,13 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             HIP_OK(hipGetLastError());
             if (g_prof_on) {
                 // counters for the roofline: one extra wait per chunk, profiling only
-                unsigned long long zero = 0, ssum = 0;
+                unsigned long long zero = 0, ssum = 0, sfirst = 0;
                 int64_t ncand = 0;
                 if (total > 0) {
                     HIP_OK(hipMemcpyAsync(steps_sum, &zero, 8, hipMemcpyHostToDevice, st));
                     hipLaunchKernelGGL(k_sum_u32, dim3(256), dim3(256), 0, st, steps, coff + nr, steps_sum);
                     HIP_OK(hipMemcpyAsync(&ssum, steps_sum, 8, hipMemcpyDeviceToHost, st));
+                    HIP_OK(hipMemcpyAsync(&sfirst, steps_first, 8, hipMemcpyDeviceToHost, st));
                 }
                 HIP_OK(hipMemcpyAsync(&ncand, coff + nr, 8, hipMemcpyDeviceToHost, st));
                 HIP_OK(hipStreamSynchronize(st));
@@ -2663,6 +2671,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 g_ctr.hits += total;
                 g_ctr.locations += ncand;
                 g_ctr.lv_steps += (int64_t)ssum;
+                g_ctr.lv_steps_first += (int64_t)sfirst;
                 if (ridx) g_ctr.second_pass_reads += nr;
             }
             r0 += nr;
