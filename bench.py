@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane per cycle
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic bytes / ops per unit, per kernel (the design notes derive them).
+# Algorithmic bytes / ops per unit, per kernel: what each unit must move or compute.
 PROBE_BYTES_PER_SLOT = 128 + 32       # one 128-byte bucket line read, one 32-byte probe record written
 GATHER_BYTES_PER_SLOT = 32            # probe record read
 GATHER_BYTES_PER_HIT = 4 + 8          # position read, hit record written
@@ -539,7 +539,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the read batch is not sharded across GPUs",
+        print(json.dumps({"error": "runs on one GPU only: the read batch is not sharded across GPUs",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

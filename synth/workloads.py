@@ -6,8 +6,9 @@ reference with substitutions and indels; Table 1 = 100/200 bp, Table 2 = 1 kb /
 is not available, so every genome and read set here is seeded and synthetic.
 
 The parameter values (s, n, d_max, c, h_max) are not given by the paper for any
-experiment (Table 3 only names them); the values below are the readings this
-project adopts, stated in the design notes.
+experiment (Table 3 only names them); the values below are readings: s = 20 and
+c = 2 throughout, n(L) = min(32, max(10, ceil(L / 100))), h_max = 300, and d_max 8
+(tiny), 10 (mid), 15 (human scale) or max(8, ceil(8 L / 100)) (mixed long reads).
 """
 from __future__ import annotations
 

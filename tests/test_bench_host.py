@@ -1,0 +1,78 @@
+"""Host-side logic of bench.py, no GPU: the HBM-traffic summary is used only for the
+kernel, workload, schedule and kernel source it was taken on; the roofline counts the
+first verification's diagonal extensions on their own; the accuracy metrics of the
+h_max harness; more than one GPU is refused with a message."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _summary(tmp_path, **kv):
+    p = tmp_path / "traffic.txt"
+    p.write_text("# comment: ignored\n" + "".join(f"{k}: {v}\n" for k, v in kv.items()))
+    return str(p)
+
+
+def test_traffic_needs_matching_kernel_source(bench, tmp_path):
+    sha = bench.kernel_source_sha1()
+    good = dict(kernel="verify", workload="mid", schedule="5,6,6,0,1,0", source_sha1=sha, bytes_per_launch=123)
+    assert bench.read_traffic(_summary(tmp_path, **good), "verify", "mid", (5, 6, 6, 0, 1, 0)) == 123
+    # the same schedule written with its defaults spelled out
+    assert bench.read_traffic(_summary(tmp_path, **good), "verify", "mid", (5, 6, 6, 0, 1, 0, 0, 0)) == 123
+    for key, bad in (("source_sha1", "0" * 40), ("kernel", "gather"), ("workload", "human"),
+                     ("schedule", "5,5,5,0,1,0")):
+        assert bench.read_traffic(_summary(tmp_path, **{**good, key: bad}), "verify", "mid", (5, 6, 6, 0, 1, 0)) is None
+    missing = {k: v for k, v in good.items() if k != "source_sha1"}
+    assert bench.read_traffic(_summary(tmp_path, **missing), "verify", "mid", (5, 6, 6, 0, 1, 0)) is None
+    assert bench.read_traffic(str(tmp_path / "absent.txt"), "verify", "mid", (5, 6, 6, 0, 1, 0)) is None
+
+
+def test_roofline_first_verification_counted_alone(bench):
+    # ms totals per kernel over 10 launches each; 1e9 steps in all, 6e8 of them first-verification
+    kern = {"verify": (10, 20.0), "verify_request": (10, 5.0), "verify_request_wave": (10, 15.0), "probe": (10, 4.0)}
+    ctr = {"lv_steps": 1_000_000_000, "lv_steps_first": 600_000_000, "seed_slots": 0, "hits": 0, "locations": 0}
+    r = bench.roofline_of(kern, ctr, "verify")
+    # 6e8 steps x 30 ops / 10 launches / 2 ms a launch
+    assert r["achieved"] == pytest.approx(6e8 * 30 / 10 / 2e-3 / 1e12, rel=1e-4)
+    assert r["bound"] == "alu" and r["unit"] == "TOP/s"
+    q = bench.roofline_of(kern, ctr, "verify_request")
+    # the request kernels share the other 4e8 steps by time: 5 of 20 ms
+    assert q["achieved"] == pytest.approx(4e8 * 0.25 * 30 / 10 / 0.5e-3 / 1e12, rel=1e-4)
+    assert bench.roofline_of(kern, ctr, "absent") is None
+    assert bench.roofline_of(kern, ctr)["kernel"] == "verify"   # the largest total
+
+
+def test_accuracy_metrics(bench):
+    truth = SimpleNamespace(n=5, truth_pos=np.array([100, 200, 300, 400, 500]), truth_strand=np.array([0, 1, 0, 1, 0]))
+    pos = np.array([100, 232, 340, 400, -1])
+    strand = np.array([0, 1, 0, 0, -1], dtype=np.int8)
+    call = np.array([1, 1, 1, 1, 0], dtype=np.int8)   # four single calls, one not found
+    out = (pos, strand, None, None, call)
+    m = bench.accuracy_of(out, truth)
+    # read 2 is 40 bases off, read 3 on the wrong strand: 2 errors of 4 aligned
+    assert m == {"aligned_pct": 80.0, "error_pct": 50.0}
+    assert bench.accuracy_of(out, truth, tol=40)["error_pct"] == 25.0
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    line = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert line and "one GPU" in json.loads(line[-1]).get("error", "") + r.stderr
