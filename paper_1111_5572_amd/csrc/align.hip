@@ -496,7 +496,6 @@ struct DedupeArgs {
     uint64_t *key;     // distinct locations (p << 1 | strand), ascending, at hoff[r]
     uint32_t *mask;    // the seed slots that voted for each
     uint32_t *count;
-    uint32_t *slot_read;   // chunk read of every reserved slot
     const uint32_t *rlist;     // the reads of this tier (null: every read of the chunk)
     const int64_t *rlist_n;
 };
@@ -560,7 +559,6 @@ __global__ __launch_bounds__(256) void k_dedupe_light(DedupeArgs a) {
             a.key[base + rank] = loc;
             a.mask[base + rank] = acc;
         }
-        if ((uint32_t)lane < H) a.slot_read[base + lane] = (uint32_t)r;
         if (lane == 0) a.count[r] = (uint32_t)__popcll(fb);
     }
 }
@@ -600,7 +598,6 @@ __global__ __launch_bounds__(256) void k_dedupe_tiny(DedupeArgs a) {
             }
         }
         if (n > 0) { a.key[base + n - 1] = cur; a.mask[base + n - 1] = acc; }
-        for (uint32_t k = 0; k < H; k++) a.slot_read[base + k] = (uint32_t)r;
         a.count[r] = n;
     }
 }
@@ -626,10 +623,7 @@ __global__ __launch_bounds__(NT) void k_dedupe_heavy(DedupeArgs a, uint64_t *gsc
         uint64_t *sk = IN_LDS ? lds_keys : gscratch + base;
         uint32_t N = 1;
         while (N < H) N <<= 1;
-        for (uint32_t i = tid; i < H; i += NT) {
-            sk[i] = a.hk[base + i];
-            a.slot_read[base + i] = (uint32_t)r;
-        }
+        for (uint32_t i = tid; i < H; i += NT) sk[i] = a.hk[base + i];
         __syncthreads();
         // k, half and j are powers of two: indices by shifts and masks
         for (uint32_t lk = 1; (1u << lk) <= N; lk++) {
@@ -688,20 +682,44 @@ __global__ __launch_bounds__(NT) void k_dedupe_heavy(DedupeArgs a, uint64_t *gsc
     }
 }
 
-// One thread per reserved slot: slot j of read r holds location j - hoff[r],
-// kept if that is below the read's count, at coff[r] + (j - hoff[r]).
-__global__ void k_compact(const int64_t *hoff, const int64_t *coff, const uint32_t *count, const uint32_t *slot_read,
-                          int64_t total, const uint64_t *key_in, const uint32_t *mask_in, uint64_t *key_out,
-                          uint32_t *mask_out, uint32_t *cread) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= total) return;
-    const uint32_t r = slot_read[j];
-    const int64_t jj = j - hoff[r];
-    if (jj >= (int64_t)count[r]) return;
-    const int64_t dst = coff[r] + jj;
-    key_out[dst] = key_in[j];
-    mask_out[dst] = mask_in[j];
-    cread[dst] = r;
+// A wave takes 64 consecutive reads (lane l: read r0 + l's first hit slot and first
+// location slot). Their kept locations fill one contiguous range of the compacted
+// arrays; the lanes take 64 of them at a time, each finding its read by a binary
+// search over the reads' first location slots in LDS, and copy location o of read r
+// from slot hoff[r] + (o - coff[r]).
+__global__ __launch_bounds__(256) void k_compact(const int64_t *hoff, const int64_t *coff, int64_t nr,
+                                                 const uint64_t *key_in, const uint32_t *mask_in, uint64_t *key_out,
+                                                 uint32_t *mask_out, uint32_t *cread) {
+    __shared__ int64_t s_src[4][64], s_dst[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r0 = wave * 64; r0 < nr; r0 += nwaves * 64) {
+        const int nrd = (int)min((int64_t)64, nr - r0);
+        const int64_t d1 = coff[r0 + nrd];
+        if (lane < nrd) {
+            s_src[wv][lane] = hoff[r0 + lane];
+            s_dst[wv][lane] = coff[r0 + lane];
+        }
+        const int64_t d0 = coff[r0];
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t o0 = d0; o0 < d1; o0 += 64) {
+            const int64_t o = o0 + lane;
+            if (o < d1) {
+                // the last read whose first location slot is at most o holds o
+                int lo = 0, hi = nrd - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_dst[wv][mid] <= o) lo = mid; else hi = mid - 1;
+                }
+                const int64_t src = s_src[wv][lo] + (o - s_dst[wv][lo]);
+                key_out[o] = key_in[src];
+                mask_out[o] = mask_in[src];
+                cread[o] = (uint32_t)(r0 + lo);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 // ----------------------------------------------------------------- verify
@@ -1993,11 +2011,11 @@ struct Layout {
     size_t total;
 };
 
-// pool arrays per slot: hit 8, location key 8 + mask 4 + slot read 4 (by read),
-// compacted key 8 + mask 4 + read 4, bucket minimum 8, capped distance 2, verified
-// limit 2, scored flag 1, verify routing lists / requests 4 + 4, requested limit 2
-constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 4 + 8 + 4 + 4 + 8 + 2 + 2 + 1 + 4 + 4 + 2;
-constexpr int POOL_ARRAYS = 14;
+// pool arrays per slot: hit 8, location key 8 + mask 4 (by read), compacted key 8 +
+// mask 4 + read 4, bucket minimum 8, capped distance 2, verified limit 2, scored flag 1,
+// verify routing lists / requests 4 + 4, requested limit 2
+constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 8 + 4 + 4 + 8 + 2 + 2 + 1 + 4 + 4 + 2;
+constexpr int POOL_ARRAYS = 13;
 
 size_t scan_tmp_bytes(int64_t items) {
     size_t b = 0;
@@ -2271,7 +2289,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         uint32_t *replay_list, *pend_local, *reqcount, *light_list;
         int64_t *req_off;
         uint64_t *hk, *key_res;
-        uint32_t *mask_res, *slot_read;
+        uint32_t *mask_res;
         uint64_t *key_c;
         uint32_t *mask_c, *cread;
         uint64_t *bmin;
@@ -2304,7 +2322,6 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         W.hk = (uint64_t *)carve(8 * (size_t)PS);
         W.key_res = (uint64_t *)carve(8 * (size_t)PS);
         W.mask_res = (uint32_t *)carve(4 * (size_t)PS);
-        W.slot_read = (uint32_t *)carve(4 * (size_t)PS);
         W.key_c = (uint64_t *)carve(8 * (size_t)PS);
         W.mask_c = (uint32_t *)carve(4 * (size_t)PS);
         W.cread = (uint32_t *)carve(4 * (size_t)PS);
@@ -2383,7 +2400,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         uint32_t *heavy_list = pend_local;   // free while a chunk replays (the next-pass list is made after)
         int64_t *req_off = W.req_off;
         uint64_t *hk = W.hk, *key_res = W.key_res;
-        uint32_t *mask_res = W.mask_res, *slot_read = W.slot_read;
+        uint32_t *mask_res = W.mask_res;
         uint64_t *key_c = W.key_c;
         uint32_t *mask_c = W.mask_c, *cread = W.cread;
         uint64_t *bmin = W.bmin;
@@ -2445,7 +2462,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + rpb - 1) / rpb, 8192));
                 timed("gather", st, [&] { hipLaunchKernelGGL(k_gather, dim3(gb), dim3(256), 0, st, ga); });
             }
-            DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, slot_read, nullptr, nullptr};
+            DedupeArgs da{hk, hits, hoff, nr, key_res, mask_res, ccount, nullptr, nullptr};
             {
                 // up to 8 hits: a lane per read; up to 64: a wave per read, from its own list
                 const unsigned tb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + 255) / 256, (int64_t)cus * 32));
@@ -2481,9 +2498,11 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             }
             tb = scan_tmp_bytes(nr + 1);
             HIP_OK(scan_excl(scan_tmp, tb, CastU32{ccount, nr}, nr + 1, coff, st));
-            if (total > 0)
-                timed("compact", st, [&] { hipLaunchKernelGGL(k_compact, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, hoff, coff, ccount,
-                                   slot_read, total, key_res, mask_res, key_c, mask_c, cread); });
+            if (total > 0) {
+                const unsigned cb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + 255) / 256, 8192));
+                timed("compact", st, [&] { hipLaunchKernelGGL(k_compact, dim3(cb), dim3(256), 0, st, hoff, coff, nr,
+                                   key_res, mask_res, key_c, mask_c, cread); });
+            }
             if (total > 0) {
                 const int64_t *ncand = coff + nr;
                 const uint32_t *slist = nullptr;
