@@ -33,8 +33,10 @@ def test_traffic_needs_matching_kernel_source(bench, tmp_path):
     sha = bench.kernel_source_sha1()
     good = dict(kernel="verify", workload="mid", schedule="5,6,6,0,1,0", source_sha1=sha, bytes_per_launch=123)
     assert bench.read_traffic(_summary(tmp_path, **good), "verify", "mid", (5, 6, 6, 0, 1, 0)) == 123
-    # the same schedule written with its defaults spelled out
+    # the same schedule written with its defaults spelled out, or with another worker count
     assert bench.read_traffic(_summary(tmp_path, **good), "verify", "mid", (5, 6, 6, 0, 1, 0, 0, 0)) == 123
+    assert bench.read_traffic(_summary(tmp_path, **good), "verify", "mid", (5, 6, 6, 0, 1, 0, 0, 3)) == 123
+    assert bench.read_traffic(_summary(tmp_path, **good), "verify", "mid", (5, 6, 6, 0, 1, 0, 4096, 0)) is None
     for key, bad in (("source_sha1", "0" * 40), ("kernel", "gather"), ("workload", "human"),
                      ("schedule", "5,5,5,0,1,0")):
         assert bench.read_traffic(_summary(tmp_path, **{**good, key: bad}), "verify", "mid", (5, 6, 6, 0, 1, 0)) is None
