@@ -188,15 +188,49 @@ __device__ inline int base_code(uint8_t b) {
 
 // Stream base x (x = STREAM_GUARD + global base index). Block t of 32 bases owns
 // code words 2t, 2t+1 and mask word t. Bases outside the reads are N.
-__global__ void k_pack(const uint8_t *reads, int64_t B, uint32_t *rcode, uint32_t *rmask, int64_t nblk) {
+// A, C, G, T in either case to 0..3 and every other byte to N, four bytes of a 32-bit
+// word at once: bits 1-2 of an ASCII letter xor-folded give the code (A 0, C 1, G 2,
+// T 3, either case), and a byte is a base when it equals a, c, g or t once bit 5 is set
+// (an exact zero-byte test on the difference). p: the four 2-bit codes (N as 0),
+// nb: the four N flags.
+__device__ inline void decode4(uint32_t w, uint32_t &p, uint32_t &nb) {
+    auto zero_bytes = [](uint32_t v) { return ~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u; };
+    const uint32_t x = w | 0x20202020u;
+    const uint32_t valid = zero_bytes(x ^ 0x61616161u) | zero_bytes(x ^ 0x63636363u) |
+                           zero_bytes(x ^ 0x67676767u) | zero_bytes(x ^ 0x74747474u);
+    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u & ((valid >> 7) * 3u);
+    const uint32_t n = ~valid & 0x80808080u;
+    p = (c & 3u) | ((c >> 6) & 0xCu) | ((c >> 12) & 0x30u) | ((c >> 18) & 0xC0u);
+    nb = ((n >> 7) & 1u) | ((n >> 14) & 2u) | ((n >> 21) & 4u) | ((n >> 28) & 8u);
+}
+
+// One thread per 32-base block of the packed stream (block t holds batch bytes
+// [32 (t - 1), 32 t); block 0 is the guard). A block wholly inside the batch reads its
+// 32 bytes as two 16-byte loads (vec: the batch is 16-byte aligned) and decodes a word
+// at a time; the guard and a partial last block go byte by byte.
+__global__ void k_pack(const uint8_t *reads, int64_t B, uint32_t *rcode, uint32_t *rmask, int64_t nblk, int vec) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nblk) return;
+    const int64_t g0 = t * 32 - STREAM_GUARD;
     uint32_t c0 = 0, c1 = 0, m = 0;
-    for (int k = 0; k < 32; k++) {
-        int64_t g = t * 32 + k - STREAM_GUARD;
-        int c = (g >= 0 && g < B) ? base_code(reads[g]) : 4;
-        if (c > 3) { m |= 1u << k; c = 0; }
-        if (k < 16) c0 |= (uint32_t)c << (2 * k); else c1 |= (uint32_t)c << (2 * (k - 16));
+    if (vec && g0 >= 0 && g0 + 32 <= B) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(reads + g0);
+        const uint4 b = *reinterpret_cast<const uint4 *>(reads + g0 + 16);
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            uint32_t p, nb;
+            decode4(w[q], p, nb);
+            if (q < 4) c0 |= p << (8 * q); else c1 |= p << (8 * (q - 4));
+            m |= nb << (4 * q);
+        }
+    } else {
+        for (int k = 0; k < 32; k++) {
+            const int64_t g = g0 + k;
+            int c = (g >= 0 && g < B) ? base_code(reads[g]) : 4;
+            if (c > 3) { m |= 1u << k; c = 0; }
+            if (k < 16) c0 |= (uint32_t)c << (2 * k); else c1 |= (uint32_t)c << (2 * (k - 16));
+        }
     }
     rcode[2 * t] = c0;
     rcode[2 * t + 1] = c1;
@@ -2358,7 +2392,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     for (int w = 0; w < workers; w++) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)wk[w].misc, 64, 0u);
     {
         const int64_t nblk = (B + STREAM_GUARD + 31) / 32 + 2;
-        timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk); });
+        const int vec = ((uintptr_t)reads & 15) == 0 ? 1 : 0;
+        timed("pack", st, [&] { hipLaunchKernelGGL(k_pack, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, reads, B, rcode, rmask, nblk, vec); });
     }
     for (int w = 1; w < workers; w++) {
         HIP_OK(hipEventRecord(leases[w - 1]->ev, st));

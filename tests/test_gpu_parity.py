@@ -234,6 +234,46 @@ def test_edge_cases(snapgpu, oracle_mod, synth_mod):
     oix.close()
 
 
+@pytest.mark.parametrize("misaligned", [False, True])
+def test_read_bytes_any_case_and_codes(snapgpu, oracle_mod, synth_mod, misaligned):
+    """Reads with lowercase bases and bytes that are not bases (IUPAC codes, punctuation,
+    0x00, bytes with the high bit set): A, C, G, T in either case are bases, every
+    other byte is N. The batch is passed 16-byte aligned (word-wise decode) and one byte
+    off (byte-wise decode)."""
+    import torch
+    from synth.workloads import TINY
+    w = TINY.scaled(genome_len=300_000, n_reads=3_000)
+    g = w.make_genome()
+    reads = w.make_reads(g)
+    rng = np.random.default_rng(21)
+    b = reads.bases.copy()
+    low = rng.random(b.size) < 0.15
+    b[low] = b[low] + 32
+    odd = rng.random(b.size) < 0.004
+    junk = np.frombuffer(b"RYKMSWBDHVNX-.@`{0\x00\xff\xc1\xe1\xd4", dtype=np.uint8)
+    b[odd] = junk[rng.integers(0, junk.size, int(odd.sum()))]
+    reads.bases = b
+    gix = snapgpu.Index(g, 20)
+    oix = oracle_mod.Index(g, 20)
+    gp = snapgpu.params_from(w.params)
+    dev = torch.device("cuda:0")
+    if misaligned:
+        whole = torch.from_numpy(np.concatenate([np.zeros(1, np.uint8), b])).to(dev)
+        rb = whole[1:]
+        assert rb.data_ptr() % 16 != 0
+    else:
+        rb = torch.from_numpy(b).to(dev)
+    ln = torch.from_numpy(reads.lengths).to(dev)
+    out = snapgpu.align(gix, rb, ln, w.params.d_max, gp, max_len=int(reads.lengths.max()))
+    torch.cuda.synchronize()
+    gout = out.numpy()
+    oout = oracle_align(oracle_mod, oix, reads, w.params)
+    nbad, rep = compare(gout, oout, reads, f"read bytes misaligned={misaligned}")
+    gix.close()
+    oix.close()
+    assert nbad == 0, rep
+
+
 def test_invalid_arguments(snapgpu, synth_mod):
     import torch
     g = synth_mod.genome_uniform(10_000, 1)
