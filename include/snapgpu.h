@@ -315,7 +315,7 @@ typedef struct {
     int64_t seed_slots;   /* (read, seed slot) probe items */
     int64_t hits;         /* seed hits gathered (h_max-passing seeds) */
     int64_t locations;    /* distinct (strand, p) locations verified */
-    int64_t lv_steps;     /* diagonal extensions run by the verify kernel */
+    int64_t lv_steps;     /* diagonal extensions run by the verify kernels */
     int64_t second_pass_reads; /* reads a first pass left to a later pass */
     int64_t requests;     /* replays of reads after the verification they asked for */
     int64_t workers;      /* most chunk workers (host thread + stream) one call used */
