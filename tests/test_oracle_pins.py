@@ -231,3 +231,23 @@ def test_simulator_error_rates(synth_mod):
     # deterministic by seed and per-read streams
     rd2 = synth_mod.simulate_reads(g, 100, 5, model)
     assert np.array_equal(rd2.bases, rd.bases[:rd2.bases.shape[0]])
+
+
+def test_family_genome_generator(synth_mod):
+    """The high-copy family generator: `copies` copies of one element at distinct,
+    non-overlapping places, each differing from the consensus at about `div` of its
+    bases (the consensus is the per-column majority over the copies)."""
+    G, copies, L, div = 400_000, 600, 300, 0.015
+    g = synth_mod.genome_family(G, 17, copies, elem_len=L, div=div)
+    assert g.shape == (G,) and set(np.unique(g).tolist()) <= set(b"ACGT")
+    # the copies sit in slots of elem_len: find them as the slots closest to the consensus
+    slots = g[: (G // L) * L].reshape(-1, L)
+    cols = np.stack([(slots == c).sum(0) for c in b"ACGT"])
+    consensus = np.frombuffer(b"ACGT", np.uint8)[cols.argmax(0)]
+    mism = (slots != consensus).mean(1)
+    family = mism < 0.2
+    assert family.sum() == copies
+    assert abs(mism[family].mean() - div) < 0.004
+    assert mism[~family].min() > 0.6    # the rest is uniform sequence
+    with pytest.raises(ValueError):
+        synth_mod.genome_family(1000, 1, 10, elem_len=300)
