@@ -78,3 +78,23 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode != 0
     line = [l for l in r.stdout.splitlines() if l.startswith("{")]
     assert line and "one GPU" in json.loads(line[-1]).get("error", "") + r.stderr
+
+
+def test_tuning_table_lookup(tmp_path):
+    """Length classes and table entries of the autotuner (no GPU needed)."""
+    sys.path.insert(0, ROOT)
+    from paper_1111_5572_amd import autotune
+    assert autotune.length_class(np.array([], np.int32)) == "empty"
+    assert autotune.length_class(np.full(100, 100, np.int32)) == "64-64"
+    assert autotune.length_class(np.full(100, 250, np.int32)) == "128-128"
+    mixed = np.concatenate([np.full(50, 100), np.full(50, 250)]).astype(np.int32)
+    assert autotune.length_class(mixed) == "64-128"
+    table = tmp_path / "t.json"
+    table.write_text(json.dumps({"plain:64-64": {"tuning": [5, 6, 6, 0, 1, 0, 0, 3]},
+                                 "batched:64-64": {"tuning": [1, 2]}}))
+    lens = np.full(10, 100, np.int32)
+    assert autotune.lookup(lens, batched=False, path=str(table)) == (5, 6, 6, 0, 1, 0, 0, 3)
+    assert autotune.lookup(lens, batched=True, path=str(table)) is None   # too few fields
+    assert autotune.lookup(np.full(10, 5000, np.int32), batched=False, path=str(table)) is None
+    # the committed table has the mid entry the benchmark uses
+    assert autotune.lookup(lens, batched=False) is not None
