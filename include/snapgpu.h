@@ -200,6 +200,10 @@ typedef struct {
                                chunk parts for */
 } snap_tuning;
 
+/* Set the process-wide schedule that snap_align (and snap_align_batched with a NULL
+ * tuning) uses from the next call on; copied, so t may be released on return.
+ * SNAP_EINVAL for a NULL pointer or a negative field. snap_get_tuning copies the
+ * current schedule into *t (SNAP_EINVAL for NULL). */
 int snap_set_tuning(const snap_tuning *t);
 int snap_get_tuning(snap_tuning *t);
 
