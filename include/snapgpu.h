@@ -32,7 +32,8 @@ enum {
     SNAP_ENOMEM = 2,   /* host or device allocation failed, or the workspace is smaller than required */
     SNAP_EDEVICE = 3,  /* a HIP runtime call or kernel launch failed */
     SNAP_EBUSY = 4,    /* the server queue is full; retry later */
-    SNAP_EAGAIN = 5    /* a polled server request has not completed yet */
+    SNAP_EAGAIN = 5,   /* a polled server request has not completed yet */
+    SNAP_EINTERNAL = 6 /* an internal consistency bound was exceeded (a library bug; outputs invalid) */
 };
 
 /* Name of a status code (static string, never NULL). */
@@ -134,7 +135,8 @@ enum { SNAP_NOT_FOUND = 0, SNAP_SINGLE = 1, SNAP_MULTIPLE = 2 };
  * Workspace bytes snap_align needs for a batch of n_reads reads holding
  * total_bases bases in all, the longest max_len. Any workspace of at least
  * this size gives identical outputs; a larger one lets the library process
- * more reads per internal pass. Returns 0 on invalid arguments.
+ * more reads per internal pass. Returns 0 on invalid arguments (NULL index or
+ * params, negative sizes, max_len above 16,384, invalid params).
  */
 size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t total_bases,
                                   int32_t max_len, int32_t d_max, const snap_params *p);
@@ -160,8 +162,10 @@ size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t
  * Results do not depend on the workspace size, the batch composition or the
  * order of reads in the batch.
  * Errors: SNAP_EINVAL (NULL or misaligned pointers, n_reads < 0, bad params,
- * d_max < 0, a read whose limit d_max(L) + c - 1 exceeds what the verify
- * kernels support), SNAP_ENOMEM (workspace too small), SNAP_EDEVICE.
+ * d_max < 0, a read longer than 16,384 bases or a negative length, a read whose
+ * limit d_max(L) + c - 1 exceeds snap_max_limit()), SNAP_ENOMEM (workspace too
+ * small), SNAP_EDEVICE, SNAP_EINTERNAL (the replay / verification loop exceeded
+ * its round bound: a library bug, never expected).
  */
 int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
                int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,

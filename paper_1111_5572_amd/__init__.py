@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsnapgpu.so")
 _lib = None
 
-SNAP_OK, SNAP_EINVAL, SNAP_ENOMEM, SNAP_EDEVICE, SNAP_EBUSY, SNAP_EAGAIN = range(6)
+SNAP_OK, SNAP_EINVAL, SNAP_ENOMEM, SNAP_EDEVICE, SNAP_EBUSY, SNAP_EAGAIN, SNAP_EINTERNAL = range(7)
 NOT_FOUND, SINGLE, MULTIPLE = 0, 1, 2
 
 

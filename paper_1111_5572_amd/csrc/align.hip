@@ -2200,7 +2200,9 @@ extern "C" int snap_get_tuning(snap_tuning *t) {
 
 extern "C" size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t total_bases,
                                              int32_t max_len, int32_t d_max, const snap_params *p) {
-    if (!ix || n_reads < 0 || total_bases < 0 || max_len < 0 || d_max < 0 || !valid_params(p)) return 0;
+    if (!ix || n_reads < 0 || total_bases < 0 || max_len < 0 || max_len > VERIFY_LMAX || d_max < 0 ||
+        !valid_params(p))
+        return 0;
     Rule rule = make_rule(ix, d_max, p);
     const int NS = seeds_for_length(rule, max_len);
     const int64_t R = std::max<int64_t>(1, std::min<int64_t>(n_reads, CHUNK_READS));
@@ -2404,7 +2406,11 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         const int Kp = std::min(Kmax, Kcap);
         // lane-per-location tile: reads up to LANE_LMAX bases with limits up to LANE_KMAX
         const int lane_L = std::min(maxL, lane_lmax), lane_K = std::min(Kp, LANE_KMAX);
-        const bool all_lane = !batched && maxL <= lane_lmax && Kp <= LANE_KMAX;
+        // every read of the batch is in the lane class exactly when the replay puts it
+        // there: it classifies a read by its full limit d_max(L) + c - 1, not by the
+        // pass's cap, so the test here uses the uncapped Kmax too (a read whose full
+        // limit is above LANE_KMAX asks for the wave tile even in a capped pass)
+        const bool all_lane = !batched && maxL <= lane_lmax && Kmax <= LANE_KMAX;
         const int RW = (std::max(lane_L, 1) + 15) / 16 + 1;
         const int TW = (std::max(lane_L, 1) + lane_K + 15) / 16 + 1;
         const int kmax_t = lane_K <= 7 ? 7 : (lane_K <= 15 ? 15 : (lane_K <= 31 ? 31 : 63));
@@ -2631,8 +2637,15 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 }
             };
             replay(ra, rb, nr);
-            // verify what the replays asked for, replay those reads, until nothing is asked
+            // verify what the replays asked for, replay those reads, until nothing is asked.
+            // A location is asked for again only at a higher limit than it was verified
+            // with, and a read's limit rises by at most c - 1 per better location found,
+            // so a read needs about NS + exact_rounds + a few times (Kmax + 1) rounds; the
+            // bound below is far above that and turns a broken invariant into an error
+            // instead of an endless loop.
+            const int max_rounds = 16 * (NSp + Kmax + 16) + exact_rounds;
             for (int round = 1;; round++) {
+                if (round > max_rounds) return SNAP_EINTERNAL;
                 int64_t nrep = 0;
                 HIP_OK(select_idx(sel_tmp, sel_tb, nr, FlagPred{rflag, RF_REPLAY}, replay_list, sel_n + 2, st));
                 HIP_OK(hipMemcpyAsync(&nrep, sel_n + 2, 8, hipMemcpyDeviceToHost, st));

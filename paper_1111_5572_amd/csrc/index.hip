@@ -352,6 +352,7 @@ extern "C" const char *snap_strerror(int code) {
         case SNAP_EDEVICE: return "HIP device error";
         case SNAP_EBUSY: return "queue full";
         case SNAP_EAGAIN: return "not complete yet";
+        case SNAP_EINTERNAL: return "internal consistency bound exceeded";
         default: return "unknown status";
     }
 }

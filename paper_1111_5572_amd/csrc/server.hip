@@ -165,9 +165,12 @@ void run_slot(snap_server *s, int k) {
              hipMemcpyAsync(h_dist, d + L.dist, 4 * (size_t)nr, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
              hipMemcpyAsync(h_second, d + L.second, 4 * (size_t)nr, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
              hipMemcpyAsync(h_strand, d + L.strand, (size_t)nr, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-             hipMemcpyAsync(h_call, d + L.call, (size_t)nr, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-             hipStreamSynchronize(sl.stream) != hipSuccess))
+             hipMemcpyAsync(h_call, d + L.call, (size_t)nr, hipMemcpyDeviceToHost, sl.stream) != hipSuccess))
             rc = SNAP_EDEVICE;
+        // on every path, success or not: the slot's staging buffers are reused by its next
+        // batch, so nothing queued on its stream (the copies in, a partly queued alignment)
+        // may still be running when they are overwritten
+        if (hipStreamSynchronize(sl.stream) != hipSuccess && rc == SNAP_OK) rc = SNAP_EDEVICE;
         const double t1 = now_s();
         int64_t o = 0;
         {

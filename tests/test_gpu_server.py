@@ -88,6 +88,34 @@ def test_results_same_alone_and_in_mix(snapgpu, oracle_mod, world):
     gix.close()
 
 
+def test_late_request_admitted_while_another_runs(snapgpu, world):
+    """Continuous batching: a request submitted once another one is on the GPU is
+    admitted into a free slot before that batch completes (its start precedes the
+    other's completion), and batches on different slots overlap in time."""
+    w, g, reads = world
+    gix = snapgpu.Index(g, 20)
+    gp = snapgpu.params_from(w.params)
+    srv = snapgpu.Server(gix, w.params.d_max, gp, slots=3, batch_reads=400, batch_bases=1_500_000,
+                         hbm_budget=6 << 30, max_waiting=100)
+    first, late = split_requests(reads, [400, 400])[:2]
+    ta = srv.submit(first.bases, first.lengths)
+    t0 = time.time()
+    while srv.stats()["busy_slots"] < 1:
+        assert time.time() - t0 < 60, "the first request was never admitted"
+        time.sleep(0.0002)
+    tb = srv.submit(late.bases, late.lengths)
+    res = drain(srv, [ta, tb])
+    (a_sub, a_start, a_done), (b_sub, b_start, b_done) = res[ta][5], res[tb][5]
+    say(f"  first {a_start - a_sub:.4f}..{a_done - a_sub:.4f}s, late {b_start - a_sub:.4f}..{b_done - a_sub:.4f}s")
+    assert b_sub < a_done and b_start < a_done, "the late request waited for the first batch to finish"
+    assert max(a_start, b_start) < min(a_done, b_done), "the two batches did not overlap"
+    for t, r in ((ta, first), (tb, late)):
+        nbad, rep = compare(res[t][:5], gpu_align(snapgpu, gix, r, w.params.d_max, gp), r, f"request {t}")
+        assert nbad == 0, rep
+    srv.close()
+    gix.close()
+
+
 def test_queue_full_and_invalid_requests(snapgpu, world):
     w, g, reads = world
     gix = snapgpu.Index(g, 20)
