@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("seeds_looked_up", "seeds_over_limit", "seeds_with_n", "candidates", "ed_calls", "ed_over_limit")]
+                ("seeds_looked_up", "seeds_over_limit", "seeds_with_n", "candidates", "ed_calls", "ed_over_limit",
+                 "lv_extensions")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -58,6 +59,10 @@ def _load():
         P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         lib.orc_index_build.argtypes = [P, i64, i32]
         lib.orc_index_build.restype = P
+        lib.orc_index_build_threads.argtypes = [P, i64, i32, i32]
+        lib.orc_index_build_threads.restype = P
+        lib.orc_index_entries.argtypes = [P, P, P, i64]
+        lib.orc_index_entries.restype = i64
         lib.orc_index_free.argtypes = [P]
         lib.orc_index_free.restype = None
         lib.orc_index_windows.argtypes = [P]
@@ -141,10 +146,14 @@ class Result:
 class Index:
     """Sorted (window, position) index of every N-free s-mer of a genome."""
 
-    def __init__(self, genome, seed_len: int = 20):
+    def __init__(self, genome, seed_len: int = 20, threads: int = 1):
+        """threads > 1 builds the same sorted array with a parallel bucket sort."""
         self.genome = _bytes(genome)
         self.seed_len = seed_len
-        self._h = _load().orc_index_build(_p(self.genome), len(self.genome), seed_len)
+        if threads > 1:
+            self._h = _load().orc_index_build_threads(_p(self.genome), len(self.genome), seed_len, threads)
+        else:
+            self._h = _load().orc_index_build(_p(self.genome), len(self.genome), seed_len)
         if not self._h:
             raise ValueError("invalid index arguments")
 
@@ -162,6 +171,14 @@ class Index:
     @property
     def windows(self) -> int:
         return int(_load().orc_index_windows(self._h))
+
+    def entries(self):
+        """The sorted (window key, position) arrays of the index."""
+        n = self.windows
+        keys = np.empty(max(n, 1), np.uint64)
+        qs = np.empty(max(n, 1), np.int64)
+        _load().orc_index_entries(self._h, _p(keys), _p(qs), n)
+        return keys[:n], qs[:n]
 
     def occ(self, seed) -> list[int] | None:
         s = _bytes(seed)

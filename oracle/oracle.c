@@ -107,6 +107,129 @@ orc_index *orc_index_build(const uint8_t *genome, int64_t len, int32_t s) {
     return ix;
 }
 
+/*
+ * The same index built by `threads` threads; the result is the same sorted array of
+ * (window, position) pairs, byte for byte. Plain bucket sort: the windows are split
+ * into contiguous ranges, one per thread; each thread counts its windows per bucket
+ * (the leading bits of the window), every (bucket, thread) pair gets its place from a
+ * prefix sum, each thread writes its pairs there, and the buckets are then sorted one
+ * by one with qsort, threads taking the next unsorted bucket in turn.
+ */
+typedef struct {
+    orc_index *ix;
+    int64_t q0, q1;        /* window range of this thread */
+    int32_t shift;         /* bucket = key >> shift */
+    int64_t *cnt;          /* per bucket: windows of this thread, then its write cursor */
+    int phase;             /* 0 count, 1 scatter */
+} build_part;
+
+typedef struct {
+    orc_index *ix;
+    const int64_t *boff;   /* bucket b spans [boff[b], boff[b+1]) */
+    int64_t nbuckets;
+    int64_t next;
+    pthread_mutex_t mu;
+} sort_job;
+
+static void *build_pass(void *arg) {
+    build_part *bp = (build_part *)arg;
+    orc_index *ix = bp->ix;
+    const int32_t s = ix->s;
+    const uint64_t mask = s >= 32 ? ~0ull : ((1ull << (2 * s)) - 1);
+    for (int64_t q = bp->q0; q < bp->q1; q++) {
+        if (has_n(ix->codes + q, s)) continue;
+        const uint64_t key = key_u64(ix->codes + q, s) & mask;
+        const int64_t b = (int64_t)(key >> bp->shift);
+        if (bp->phase == 0) {
+            bp->cnt[b]++;
+        } else {
+            entry *e = &ix->e[bp->cnt[b]++];
+            e->key = key;
+            e->q = q;
+        }
+    }
+    return NULL;
+}
+
+static void *sort_buckets(void *arg) {
+    sort_job *sj = (sort_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&sj->mu);
+        const int64_t b = sj->next++;
+        pthread_mutex_unlock(&sj->mu);
+        if (b >= sj->nbuckets) break;
+        const int64_t n = sj->boff[b + 1] - sj->boff[b];
+        if (n > 1) qsort(sj->ix->e + sj->boff[b], (size_t)n, sizeof(entry), cmp_entry);
+    }
+    return NULL;
+}
+
+orc_index *orc_index_build_threads(const uint8_t *genome, int64_t len, int32_t s, int32_t threads) {
+    if (threads <= 1) return orc_index_build(genome, len, s);
+    if (s < 1 || s > 32 || len < 0) return NULL;
+    if (threads > 256) threads = 256;
+    orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
+    ix->s = s;
+    ix->G = len;
+    ix->codes = (uint8_t *)malloc(len > 0 ? (size_t)len : 1);
+    for (int64_t i = 0; i < len; i++) ix->codes[i] = (uint8_t)code_of(genome[i]);
+    const int64_t nwin = len >= s ? len - s + 1 : 0;
+    const int32_t bits = 2 * s < 16 ? 2 * s : 16;
+    const int64_t nb = (int64_t)1 << bits;
+    build_part *bp = (build_part *)calloc((size_t)threads, sizeof(build_part));
+    pthread_t th[256];
+    for (int32_t t = 0; t < threads; t++) {
+        bp[t].ix = ix;
+        bp[t].q0 = nwin * t / threads;
+        bp[t].q1 = nwin * (t + 1) / threads;
+        bp[t].shift = 2 * s - bits;
+        bp[t].cnt = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+        bp[t].phase = 0;
+        pthread_create(&th[t], NULL, build_pass, &bp[t]);
+    }
+    for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+    /* bucket b, thread t writes from boff[b] + (windows of b in threads before t) */
+    int64_t *boff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+    int64_t m = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        boff[b] = m;
+        for (int32_t t = 0; t < threads; t++) {
+            const int64_t c = bp[t].cnt[b];
+            bp[t].cnt[b] = m;
+            m += c;
+        }
+    }
+    boff[nb] = m;
+    ix->n = m;
+    ix->e = (entry *)malloc((size_t)(m > 0 ? m : 1) * sizeof(entry));
+    for (int32_t t = 0; t < threads; t++) {
+        bp[t].phase = 1;
+        pthread_create(&th[t], NULL, build_pass, &bp[t]);
+    }
+    for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+    sort_job sj;
+    sj.ix = ix;
+    sj.boff = boff;
+    sj.nbuckets = nb;
+    sj.next = 0;
+    pthread_mutex_init(&sj.mu, NULL);
+    for (int32_t t = 0; t < threads; t++) pthread_create(&th[t], NULL, sort_buckets, &sj);
+    for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&sj.mu);
+    for (int32_t t = 0; t < threads; t++) free(bp[t].cnt);
+    free(bp);
+    free(boff);
+    return ix;
+}
+
+int64_t orc_index_entries(const orc_index *ix, uint64_t *keys, int64_t *qs, int64_t cap) {
+    for (int64_t i = 0; i < ix->n && i < cap; i++) {
+        keys[i] = ix->e[i].key;
+        qs[i] = ix->e[i].q;
+    }
+    return ix->n;
+}
+
 void orc_index_free(orc_index *ix) {
     if (!ix) return;
     free(ix->codes);
@@ -341,6 +464,13 @@ static void score(const orc_index *ix, work *w, state *st, int64_t k, int32_t L,
     cd->scored = 1;
     stt->ed_calls++;
     if (d >= ORC_INF) stt->ed_over_limit++;
+    if (lim >= 0) {
+        /* statistic only: the diagonal extensions a furthest-reaching-diagonal evaluation
+         * of this call runs at its own limit (rounds e = 0 .. min(D, lim), 2e + 1 diagonals
+         * each); the distance above comes from the full table */
+        const int64_t e = d < lim ? d : lim;
+        stt->lv_extensions += (e + 1) * (e + 1);
+    }
     if (lg && lg->n < lg->cap) {
         lg->p[lg->n] = cd->p; lg->strand[lg->n] = (int8_t)cd->strand; lg->d[lg->n] = d; lg->lim[lg->n] = lim;
         lg->n++;
@@ -483,6 +613,7 @@ static void *worker(void *arg) {
     jb->total.candidates += stt.candidates;
     jb->total.ed_calls += stt.ed_calls;
     jb->total.ed_over_limit += stt.ed_over_limit;
+    jb->total.lv_extensions += stt.lv_extensions;
     pthread_mutex_unlock(&jb->mu);
     work_free(&w);
     return NULL;

@@ -39,10 +39,17 @@ typedef struct {
     int64_t candidates;        /* distinct (strand, p) locations that received a vote */
     int64_t ed_calls;          /* EditDistance calls */
     int64_t ed_over_limit;     /* calls that returned the special value */
+    int64_t lv_extensions;     /* sum over calls of (min(D, limit) + 1)^2: the diagonal extensions a
+                                  furthest-reaching-diagonal evaluation runs at each call's own limit */
 } orc_stats;
 
 /* Index: every N-free window of length s, as sorted (key, position) pairs. */
 orc_index *orc_index_build(const uint8_t *genome, int64_t len, int32_t s);
+/* The same index (identical sorted array) built by `threads` threads with a bucket sort;
+ * threads <= 1 is orc_index_build. */
+orc_index *orc_index_build_threads(const uint8_t *genome, int64_t len, int32_t s, int32_t threads);
+/* Copies up to cap (window key, position) pairs of the sorted array; returns the count. */
+int64_t orc_index_entries(const orc_index *ix, uint64_t *keys, int64_t *qs, int64_t cap);
 void orc_index_free(orc_index *ix);
 int64_t orc_index_windows(const orc_index *ix);
 /* Positions q with genome[q, q+s) == the s bases at `seed` (ASCII); -1 if the seed holds an N.

@@ -91,6 +91,8 @@ def test_third_limit_rejects_a_location_at_d_best(oracle_mod, bg, R, strand):
     assert log == [(5000, strand, 2, 9), (12000, strand, 3, 3), (16000, strand, INF, 1)]
     assert out == (5000, strand, 2, 3, 2)
     assert st["seeds_looked_up"] == 4 and st["ed_calls"] == 3
+    # diagonal extensions at each call's own limit, (min(D, limit) + 1)^2: 9 + 16 + 4
+    assert st["lv_extensions"] == 29
 
 
 @pytest.mark.parametrize("strand", [0, 1])

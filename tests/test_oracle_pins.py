@@ -179,6 +179,27 @@ def test_index_vs_occurrence_scan(oracle_mod, synth_mod):
         ix.close()
 
 
+@pytest.mark.parametrize("s,threads", [(8, 3), (20, 2), (20, 8), (3, 5), (32, 4)])
+def test_parallel_index_build_equals_plain(oracle_mod, synth_mod, s, threads):
+    """The threaded bucket-sort build gives the same sorted (window, position) array as
+    the plain single-thread build, on a repeat genome with N runs (and answers lookups
+    the same, against a scan of the genome)."""
+    g = synth_mod.genome_repeats(40_000, 13, n_frac=0.02, n_run_lo=50, n_run_hi=500)
+    a = oracle_mod.Index(g, s)
+    b = oracle_mod.Index(g, s, threads=threads)
+    ka, qa = a.entries()
+    kb, qb = b.entries()
+    assert len(ka) == a.windows > 0
+    assert np.array_equal(ka, kb) and np.array_equal(qa, qb)
+    gs = g.tobytes().decode()
+    rnd = random.Random(s)
+    for q in rnd.sample(range(len(gs) - s), 30):
+        want = None if "N" in gs[q:q + s] else [x for x in range(len(gs) - s + 1) if gs[x:x + s] == gs[q:q + s]]
+        assert b.occ(gs[q:q + s]) == want
+    a.close()
+    b.close()
+
+
 def test_index_random_hit_rate(oracle_mod, synth_mod):
     """Section 3.1: a random s-mer hits about G/4^s places by chance (4^6 for
     s = 10 and 4^-4 for s = 20 on a 4^16 genome). Checked at s = 7 where the
