@@ -131,14 +131,22 @@ typedef struct {
     pthread_mutex_t mu;
 } sort_job;
 
+/* Windows [q0, q1): the key of each is kept rolling (two bits in, two bits out) and a
+ * window holds an N exactly when the last N seen lies inside it. */
 static void *build_pass(void *arg) {
     build_part *bp = (build_part *)arg;
     orc_index *ix = bp->ix;
     const int32_t s = ix->s;
     const uint64_t mask = s >= 32 ? ~0ull : ((1ull << (2 * s)) - 1);
-    for (int64_t q = bp->q0; q < bp->q1; q++) {
-        if (has_n(ix->codes + q, s)) continue;
-        const uint64_t key = key_u64(ix->codes + q, s) & mask;
+    if (bp->q1 <= bp->q0) return NULL;
+    uint64_t key = 0;
+    int64_t last_n = bp->q0 - 1;
+    for (int64_t i = bp->q0; i < bp->q1 + s - 1; i++) {
+        int c = ix->codes[i];
+        if (c > 3) { last_n = i; c = 0; }
+        key = ((key << 2) | (uint64_t)c) & mask;
+        const int64_t q = i - s + 1;
+        if (q < bp->q0 || last_n >= q) continue;
         const int64_t b = (int64_t)(key >> bp->shift);
         if (bp->phase == 0) {
             bp->cnt[b]++;
@@ -148,6 +156,14 @@ static void *build_pass(void *arg) {
             e->q = q;
         }
     }
+    return NULL;
+}
+
+typedef struct { const uint8_t *genome; uint8_t *codes; int64_t a, b; } code_part;
+
+static void *code_pass(void *arg) {
+    code_part *cp = (code_part *)arg;
+    for (int64_t i = cp->a; i < cp->b; i++) cp->codes[i] = (uint8_t)code_of(cp->genome[i]);
     return NULL;
 }
 
@@ -172,12 +188,20 @@ orc_index *orc_index_build_threads(const uint8_t *genome, int64_t len, int32_t s
     ix->s = s;
     ix->G = len;
     ix->codes = (uint8_t *)malloc(len > 0 ? (size_t)len : 1);
-    for (int64_t i = 0; i < len; i++) ix->codes[i] = (uint8_t)code_of(genome[i]);
+    code_part cp[256];
+    pthread_t th[256];
+    for (int32_t t = 0; t < threads; t++) {
+        cp[t].genome = genome;
+        cp[t].codes = ix->codes;
+        cp[t].a = len * t / threads;
+        cp[t].b = len * (t + 1) / threads;
+        pthread_create(&th[t], NULL, code_pass, &cp[t]);
+    }
+    for (int32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
     const int64_t nwin = len >= s ? len - s + 1 : 0;
     const int32_t bits = 2 * s < 16 ? 2 * s : 16;
     const int64_t nb = (int64_t)1 << bits;
     build_part *bp = (build_part *)calloc((size_t)threads, sizeof(build_part));
-    pthread_t th[256];
     for (int32_t t = 0; t < threads; t++) {
         bp[t].ix = ix;
         bp[t].q0 = nwin * t / threads;
