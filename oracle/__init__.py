@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("seeds_looked_up", "seeds_over_limit", "seeds_with_n", "candidates", "ed_calls", "ed_over_limit",
-                 "lv_extensions")]
+                 "lv_extensions", "index_lookups")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -61,6 +61,10 @@ def _load():
         lib.orc_index_build.restype = P
         lib.orc_index_build_threads.argtypes = [P, i64, i32, i32]
         lib.orc_index_build_threads.restype = P
+        lib.orc_index_build_strided.argtypes = [P, i64, i32, i32, i32]
+        lib.orc_index_build_strided.restype = P
+        lib.orc_index_stride.argtypes = [P]
+        lib.orc_index_stride.restype = i32
         lib.orc_index_entries.argtypes = [P, P, P, i64]
         lib.orc_index_entries.restype = i64
         lib.orc_index_free.argtypes = [P]
@@ -146,11 +150,15 @@ class Result:
 class Index:
     """Sorted (window, position) index of every N-free s-mer of a genome."""
 
-    def __init__(self, genome, seed_len: int = 20, threads: int = 1):
-        """threads > 1 builds the same sorted array with a parallel bucket sort."""
+    def __init__(self, genome, seed_len: int = 20, threads: int = 1, stride: int = 1):
+        """threads > 1 builds the same sorted array with a parallel bucket sort; stride > 1
+        indexes only the windows at multiples of the stride."""
         self.genome = _bytes(genome)
         self.seed_len = seed_len
-        if threads > 1:
+        self.stride = stride
+        if stride != 1:
+            self._h = _load().orc_index_build_strided(_p(self.genome), len(self.genome), seed_len, stride, threads)
+        elif threads > 1:
             self._h = _load().orc_index_build_threads(_p(self.genome), len(self.genome), seed_len, threads)
         else:
             self._h = _load().orc_index_build(_p(self.genome), len(self.genome), seed_len)

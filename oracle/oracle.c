@@ -50,6 +50,7 @@ typedef struct { uint64_t key; int64_t q; } entry;
 
 struct orc_index {
     int32_t s;
+    int32_t stride;   /* windows at positions q with q % stride == 0 are indexed */
     int64_t G;
     uint8_t *codes;   /* genome as codes 0..4 */
     int64_t n;        /* number of N-free windows */
@@ -85,19 +86,25 @@ static int cmp_entry(const void *a, const void *b) {
     return 0;
 }
 
-orc_index *orc_index_build(const uint8_t *genome, int64_t len, int32_t s) {
-    if (s < 1 || s > 32 || len < 0) return NULL;
+/*
+ * Strided index (the footnote to "Overlapping Seeds" in Section 3.1): a window slid
+ * `stride` bases at a time instead of one, i.e. only the windows at positions that are
+ * multiples of the stride are indexed; stride 1 is the index of every overlapping window.
+ */
+static orc_index *build_plain(const uint8_t *genome, int64_t len, int32_t s, int32_t stride) {
+    if (s < 1 || s > 32 || len < 0 || stride < 1) return NULL;
     orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
     ix->s = s;
+    ix->stride = stride;
     ix->G = len;
     ix->codes = (uint8_t *)malloc(len > 0 ? (size_t)len : 1);
     for (int64_t i = 0; i < len; i++) ix->codes[i] = (uint8_t)code_of(genome[i]);
     int64_t m = 0;
-    for (int64_t q = 0; q + s <= len; q++) if (!has_n(ix->codes + q, s)) m++;
+    for (int64_t q = 0; q + s <= len; q++) if (q % stride == 0 && !has_n(ix->codes + q, s)) m++;
     ix->e = (entry *)malloc((size_t)(m > 0 ? m : 1) * sizeof(entry));
     m = 0;
     for (int64_t q = 0; q + s <= len; q++) {
-        if (has_n(ix->codes + q, s)) continue;
+        if (q % stride != 0 || has_n(ix->codes + q, s)) continue;
         ix->e[m].key = key_u64(ix->codes + q, s);
         ix->e[m].q = q;
         m++;
@@ -106,6 +113,8 @@ orc_index *orc_index_build(const uint8_t *genome, int64_t len, int32_t s) {
     qsort(ix->e, (size_t)m, sizeof(entry), cmp_entry);
     return ix;
 }
+
+orc_index *orc_index_build(const uint8_t *genome, int64_t len, int32_t s) { return build_plain(genome, len, s, 1); }
 
 /*
  * The same index built by `threads` threads; the result is the same sorted array of
@@ -146,7 +155,7 @@ static void *build_pass(void *arg) {
         if (c > 3) { last_n = i; c = 0; }
         key = ((key << 2) | (uint64_t)c) & mask;
         const int64_t q = i - s + 1;
-        if (q < bp->q0 || last_n >= q) continue;
+        if (q < bp->q0 || last_n >= q || q % ix->stride != 0) continue;
         const int64_t b = (int64_t)(key >> bp->shift);
         if (bp->phase == 0) {
             bp->cnt[b]++;
@@ -180,12 +189,14 @@ static void *sort_buckets(void *arg) {
     return NULL;
 }
 
-orc_index *orc_index_build_threads(const uint8_t *genome, int64_t len, int32_t s, int32_t threads) {
-    if (threads <= 1) return orc_index_build(genome, len, s);
-    if (s < 1 || s > 32 || len < 0) return NULL;
+orc_index *orc_index_build_strided(const uint8_t *genome, int64_t len, int32_t s, int32_t stride,
+                                   int32_t threads) {
+    if (threads <= 1) return build_plain(genome, len, s, stride);
+    if (s < 1 || s > 32 || len < 0 || stride < 1) return NULL;
     if (threads > 256) threads = 256;
     orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
     ix->s = s;
+    ix->stride = stride;
     ix->G = len;
     ix->codes = (uint8_t *)malloc(len > 0 ? (size_t)len : 1);
     code_part cp[256];
@@ -245,6 +256,12 @@ orc_index *orc_index_build_threads(const uint8_t *genome, int64_t len, int32_t s
     free(boff);
     return ix;
 }
+
+orc_index *orc_index_build_threads(const uint8_t *genome, int64_t len, int32_t s, int32_t threads) {
+    return orc_index_build_strided(genome, len, s, 1, threads);
+}
+
+int32_t orc_index_stride(const orc_index *ix) { return ix->stride; }
 
 int64_t orc_index_entries(const orc_index *ix, uint64_t *keys, int64_t *qs, int64_t cap) {
     for (int64_t i = 0; i < ix->n && i < cap; i++) {
@@ -383,8 +400,11 @@ int32_t orc_edit_distance(const uint8_t *read, int32_t L, const uint8_t *text, i
 typedef struct { int64_t p; int32_t strand; int32_t hits; int32_t scored; } cand;
 typedef struct { int32_t strand; int64_t bkey; int32_t d; int64_t p; } bucket;
 
+typedef struct { int64_t p; int32_t strand; } vkey;
+
 typedef struct {
     cand *c; int64_t nc, capc;
+    vkey *v; int64_t nv, capv;   /* one slot's locations before they are voted */
     bucket *b; int64_t nb, capb;
     uint8_t *fwd, *rc; int32_t capL;
     int32_t offs[64];
@@ -396,7 +416,23 @@ typedef struct {
     int32_t best_strand;
 } state;
 
-static void work_free(work *w) { free(w->c); free(w->b); free(w->fwd); free(w->rc); }
+static void work_free(work *w) { free(w->c); free(w->v); free(w->b); free(w->fwd); free(w->rc); }
+
+static void slot_add(work *w, int64_t p, int32_t strand) {
+    if (w->nv == w->capv) {
+        w->capv = w->capv ? 2 * w->capv : 64;
+        w->v = (vkey *)realloc(w->v, sizeof(vkey) * (size_t)w->capv);
+    }
+    w->v[w->nv].p = p;
+    w->v[w->nv].strand = strand;
+    w->nv++;
+}
+
+static int cmp_vkey(const void *a, const void *b) {
+    const vkey *x = (const vkey *)a, *y = (const vkey *)b;
+    if (x->p != y->p) return x->p < y->p ? -1 : 1;
+    return (x->strand > y->strand) - (x->strand < y->strand);
+}
 
 /* SeedsHitting[(strand, p)] += 1, the map kept sorted by (p, strand). */
 static void vote(work *w, int64_t p, int32_t strand) {
@@ -519,6 +555,14 @@ static void score(const orc_index *ix, work *w, state *st, int64_t k, int32_t L,
  *    before each call, and does not apply the early multiple-hits return;
  *  - "all seeds had > h_max entries" means at least one seed was looked up and
  *    every looked-up seed was over h_max.
+ * With a strided index (stride > 1, Section 3.1's footnote) a seed slot at offset o
+ * looks up the seeds at o, o + 1, ..., o + stride - 1 that fit the read: whatever the
+ * location, one of them starts at an indexed position of it. The slot is skipped as a
+ * seed with an N if any of those bases is an N; its entries for the h_max test are the
+ * sum over its seeds; it votes once for each location any of its seeds hit; and it
+ * counts in t only if it is a round-0 slot all of whose stride seeds fit (then the
+ * round-0 slots cover disjoint stretches of the read for any one location, as with the
+ * full index). With stride 1 every rule above is the plain one.
  * The state at termination is reported: best location, strand, d_best, d_second.
  */
 static void align_one(const orc_index *ix, work *w, const uint8_t *read, int32_t L, const orc_params *pr,
@@ -540,27 +584,43 @@ static void align_one(const orc_index *ix, work *w, const uint8_t *read, int32_t
     state st = {ORC_INF, ORC_INF, -1, -1};
     int32_t t = 0, looked = 0, all_over = 1, call = -1;
     uint8_t rcseed[32];
+    const int32_t stride = ix->stride;
     for (int32_t i = 0; i < nseeds && call < 0; i++) {
         const int32_t o = w->offs[i];
-        const uint8_t *S = w->fwd + o;
-        if (has_n(S, s)) { stt->seeds_with_n++; continue; }
-        for (int32_t k = 0; k < s; k++) rcseed[k] = (uint8_t)comp_code(S[s - 1 - k]);
-        int64_t flo, fhi, rlo, rhi;
-        occ_range(ix, key_u64(S, s), &flo, &fhi);
-        occ_range(ix, key_u64(rcseed, s), &rlo, &rhi);
+        /* the slot's seeds: offsets o, o + 1, ..., o + stride - 1, those that fit the read
+         * (with stride 1, the one seed at o); one of them is aligned with the index's
+         * stride for any location */
+        int32_t np = 0;
+        while (np < stride && o + np + s <= L) np++;
+        if (has_n(w->fwd + o, s + np - 1)) { stt->seeds_with_n++; continue; }
+        int64_t entries = 0;
+        w->nv = 0;
+        for (int32_t j = 0; j < np; j++) {
+            const uint8_t *S = w->fwd + o + j;
+            for (int32_t k = 0; k < s; k++) rcseed[k] = (uint8_t)comp_code(S[s - 1 - k]);
+            int64_t flo, fhi, rlo, rhi;
+            occ_range(ix, key_u64(S, s), &flo, &fhi);
+            occ_range(ix, key_u64(rcseed, s), &rlo, &rhi);
+            stt->index_lookups++;
+            entries += (fhi - flo) + (rhi - rlo);
+            for (int64_t e = flo; e < fhi; e++) {
+                int64_t p = ix->e[e].q - (o + j);
+                if (p >= 0 && p + L <= ix->G) slot_add(w, p, 0);
+            }
+            for (int64_t e = rlo; e < rhi; e++) {
+                int64_t p = ix->e[e].q - (L - (o + j) - s);
+                if (p >= 0 && p + L <= ix->G) slot_add(w, p, 1);
+            }
+        }
         looked = 1;
         stt->seeds_looked_up++;
-        if ((fhi - flo) + (rhi - rlo) > hmax) { stt->seeds_over_limit++; continue; }
+        if (entries > hmax) { stt->seeds_over_limit++; continue; }
         all_over = 0;
-        for (int64_t e = flo; e < fhi; e++) {
-            int64_t p = ix->e[e].q - o;
-            if (p >= 0 && p + L <= ix->G) vote(w, p, 0);
-        }
-        for (int64_t e = rlo; e < rhi; e++) {
-            int64_t p = ix->e[e].q - (L - o - s);
-            if (p >= 0 && p + L <= ix->G) vote(w, p, 1);
-        }
-        if (o % s == 0) t++;
+        /* one vote per location per slot */
+        qsort(w->v, (size_t)w->nv, sizeof(vkey), cmp_vkey);
+        for (int64_t e = 0; e < w->nv; e++)
+            if (e == 0 || cmp_vkey(&w->v[e], &w->v[e - 1]) != 0) vote(w, w->v[e].p, w->v[e].strand);
+        if (o % s == 0 && np == stride) t++;
         int64_t k = select_unscored(w);
         if (k >= 0) score(ix, w, &st, k, L, dmax, pr, stt, lg);
         if (st.d_best < c && st.d_second < st.d_best + c) {
@@ -638,6 +698,7 @@ static void *worker(void *arg) {
     jb->total.ed_calls += stt.ed_calls;
     jb->total.ed_over_limit += stt.ed_over_limit;
     jb->total.lv_extensions += stt.lv_extensions;
+    jb->total.index_lookups += stt.index_lookups;
     pthread_mutex_unlock(&jb->mu);
     work_free(&w);
     return NULL;

@@ -41,6 +41,7 @@ typedef struct {
     int64_t ed_over_limit;     /* calls that returned the special value */
     int64_t lv_extensions;     /* sum over calls of (min(D, limit) + 1)^2: the diagonal extensions a
                                   furthest-reaching-diagonal evaluation runs at each call's own limit */
+    int64_t index_lookups;     /* seeds looked up in the index (stride per seed slot with a strided index) */
 } orc_stats;
 
 /* Index: every N-free window of length s, as sorted (key, position) pairs. */
@@ -48,6 +49,12 @@ orc_index *orc_index_build(const uint8_t *genome, int64_t len, int32_t s);
 /* The same index (identical sorted array) built by `threads` threads with a bucket sort;
  * threads <= 1 is orc_index_build. */
 orc_index *orc_index_build_threads(const uint8_t *genome, int64_t len, int32_t s, int32_t threads);
+/* Strided index (Section 3.1, footnote to "Overlapping Seeds"): only the windows at positions
+ * q with q % stride == 0; stride 1 is orc_index_build_threads. Alignment with such an index
+ * looks up `stride` consecutive seeds per seed slot (see orc_align). */
+orc_index *orc_index_build_strided(const uint8_t *genome, int64_t len, int32_t s, int32_t stride,
+                                   int32_t threads);
+int32_t orc_index_stride(const orc_index *ix);
 /* Copies up to cap (window key, position) pairs of the sorted array; returns the count. */
 int64_t orc_index_entries(const orc_index *ix, uint64_t *keys, int64_t *qs, int64_t cap);
 void orc_index_free(orc_index *ix);
