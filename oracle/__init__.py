@@ -67,6 +67,8 @@ def _load():
         lib.orc_index_stride.restype = i32
         lib.orc_index_entries.argtypes = [P, P, P, i64]
         lib.orc_index_entries.restype = i64
+        lib.orc_dup_classes.argtypes = [P, i64, i64, P]
+        lib.orc_dup_classes.restype = i32
         lib.orc_index_free.argtypes = [P]
         lib.orc_index_free.restype = None
         lib.orc_index_windows.argtypes = [P]
@@ -117,6 +119,15 @@ def edit_distance(read, text, lim: int) -> int:
     """Bounded edit distance (start anchored, end free); INF above lim."""
     r, t = _bytes(read), _bytes(text)
     return int(_load().orc_edit_distance(_p(r), len(r), _p(t), len(t), lim))
+
+
+def dup_classes(genome, W: int) -> np.ndarray:
+    """rep[p]: the smallest position whose W-base window equals p's (exact duplicates)."""
+    g = _bytes(genome)
+    rep = np.empty(max(len(g), 1), np.int64)
+    if _load().orc_dup_classes(_p(g), len(g), W, _p(rep)) != 0:
+        raise ValueError("invalid sizes")
+    return rep[:len(g)]
 
 
 def seed_offsets(L: int, s: int, n: int) -> list[int]:

@@ -657,6 +657,49 @@ int32_t orc_align_log(const orc_index *ix, const uint8_t *read, int32_t L, const
     return lg.n;
 }
 
+/* ----------------------------------------------- exact-duplicate classes */
+
+/*
+ * Section 4.2, "Approach": regions of exact duplication are found by looking for
+ * identical substrings of a read's length, so that a read is compared with each
+ * repeated string only once. Reading: the string a read of length L is compared with at
+ * location p is the text window G[p, p + L + K) (the edit distance of Section 3.2 at any
+ * limit up to K = d_max + c - 1 never looks further), so two locations whose windows of
+ * W >= L + K bases are identical give the same distance at every limit, and the
+ * distance needs computing once per class of identical windows. Here the classes are
+ * the definition written out: rep[p] is the smallest p' whose W-base window equals p's
+ * (bases compared as codes, every N equal to every N; a window is identical only as a
+ * whole), found by sorting the positions by window content; a position whose window
+ * would run past the genome's end is its own class.
+ */
+static const uint8_t *dup_codes;
+static int64_t dup_W;
+
+static int cmp_window(const void *a, const void *b) {
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    const int c = memcmp(dup_codes + x, dup_codes + y, (size_t)dup_W);
+    if (c) return c;
+    return (x > y) - (x < y);
+}
+
+int32_t orc_dup_classes(const uint8_t *genome, int64_t len, int64_t W, int64_t *rep) {
+    if (len < 0 || W < 1) return -1;
+    uint8_t *codes = (uint8_t *)malloc(len > 0 ? (size_t)len : 1);
+    for (int64_t i = 0; i < len; i++) codes[i] = (uint8_t)code_of(genome[i]);
+    for (int64_t p = 0; p < len; p++) rep[p] = p;
+    const int64_t n = len >= W ? len - W + 1 : 0;
+    int64_t *order = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t p = 0; p < n; p++) order[p] = p;
+    dup_codes = codes;   /* qsort has no context argument; the oracle's callers are serial */
+    dup_W = W;
+    qsort(order, (size_t)n, sizeof(int64_t), cmp_window);
+    for (int64_t k = 1; k < n; k++)
+        if (memcmp(codes + order[k], codes + order[k - 1], (size_t)W) == 0) rep[order[k]] = rep[order[k - 1]];
+    free(order);
+    free(codes);
+    return 0;
+}
+
 /* ------------------------------------------------------ multi-core driver */
 
 /*

@@ -85,6 +85,11 @@ int32_t orc_align(const orc_index *ix, const uint8_t *reads, const int64_t *offs
 int32_t orc_align_log(const orc_index *ix, const uint8_t *read, int32_t L, const orc_params *p,
                       int64_t *log_p, int8_t *log_strand, int32_t *log_d, int32_t *log_lim, int32_t cap);
 
+/* Exact-duplicate classes of the genome's W-base windows (Section 4.2, "Approach"): rep[p]
+ * (len entries) = the smallest position whose W-base window equals p's, or p itself (also for
+ * positions whose window runs past the end). Not thread-safe. Returns 0, or -1 for bad sizes. */
+int32_t orc_dup_classes(const uint8_t *genome, int64_t len, int64_t W, int64_t *rep);
+
 #ifdef __cplusplus
 }
 #endif
