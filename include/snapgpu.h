@@ -33,7 +33,8 @@ enum {
     SNAP_EDEVICE = 3,  /* a HIP runtime call or kernel launch failed */
     SNAP_EBUSY = 4,    /* the server queue is full; retry later */
     SNAP_EAGAIN = 5,   /* a polled server request has not completed yet */
-    SNAP_EINTERNAL = 6 /* an internal consistency bound was exceeded (a library bug; outputs invalid) */
+    SNAP_EINTERNAL = 6, /* an internal consistency bound was exceeded (a library bug; outputs invalid) */
+    SNAP_ETOOBIG = 7    /* snap_align_noalloc: the batch needs more scratch than its fixed array holds */
 };
 
 /* Name of a status code (static string, never NULL). */
@@ -170,6 +171,33 @@ size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t
 int snap_align(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
                int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,
                int32_t *second, int8_t *call, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * snap_align without a workspace, for callers that cannot allocate device memory
+ * (code that must not call hipMalloc: tight serving loops, harnesses that forbid
+ * allocation). The same arguments and outputs as snap_align, minus workspace and
+ * ws_bytes; the same kernels, run by one host worker on the given stream, and the
+ * same outputs.
+ * Scratch: a fixed array of snap_align_noalloc_scratch_bytes() bytes (128 MiB) per
+ * device, part of the library's device code (placed when the library is loaded on
+ * that device, held until the process ends). The call allocates no device memory and
+ * creates no stream. It clears what it needs itself, so a call never sees what an
+ * earlier one left there. Every call on one device shares that device's array:
+ * calls that overlap on one device (several host threads, or several streams
+ * without waits between the calls) race and give wrong outputs; serialize them.
+ * Size limit: a batch is taken exactly when snap_align_workspace_bytes(ix, n_reads,
+ * sum of lengths, longest length, d_max, p) <= snap_align_noalloc_scratch_bytes()
+ * (about 70,000 reads of 100 bp); a larger batch returns SNAP_ETOOBIG before any
+ * output is written. Split it, or use snap_align with a workspace.
+ * Errors: as snap_align (SNAP_EINVAL, SNAP_EDEVICE, SNAP_EINTERNAL), plus
+ * SNAP_ETOOBIG.
+ */
+int snap_align_noalloc(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
+                       int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,
+                       int32_t *second, int8_t *call, void *stream);
+
+/* Bytes of snap_align_noalloc's fixed scratch array on each device. */
+size_t snap_align_noalloc_scratch_bytes(void);
 
 /* Largest limit d_max(L) + c - 1 the verify kernels accept. */
 int32_t snap_max_limit(void);

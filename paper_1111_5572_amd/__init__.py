@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsnapgpu.so")
 _lib = None
 
-SNAP_OK, SNAP_EINVAL, SNAP_ENOMEM, SNAP_EDEVICE, SNAP_EBUSY, SNAP_EAGAIN, SNAP_EINTERNAL = range(7)
+SNAP_OK, SNAP_EINVAL, SNAP_ENOMEM, SNAP_EDEVICE, SNAP_EBUSY, SNAP_EAGAIN, SNAP_EINTERNAL, SNAP_ETOOBIG = range(8)
 NOT_FOUND, SINGLE, MULTIPLE = 0, 1, 2
 
 
@@ -136,6 +136,10 @@ def lib():
         L.snap_align_workspace_bytes.restype = sz
         L.snap_align.argtypes = [P, P, P, i64, i32, ctypes.POINTER(Params), P, P, P, P, P, P, sz, P]
         L.snap_align.restype = ctypes.c_int
+        L.snap_align_noalloc.argtypes = [P, P, P, i64, i32, ctypes.POINTER(Params), P, P, P, P, P, P]
+        L.snap_align_noalloc.restype = ctypes.c_int
+        L.snap_align_noalloc_scratch_bytes.argtypes = []
+        L.snap_align_noalloc_scratch_bytes.restype = sz
         L.snap_max_limit.argtypes = []
         L.snap_max_limit.restype = i32
         L.snap_debug_host_lookup.argtypes = [P, u64, i32, P, i64, P, P, P, ctypes.POINTER(u64)]
@@ -331,6 +335,22 @@ def align(index: Index, reads, lengths, d_max: int, params: Params | None = None
                             out.pos.data_ptr(), out.strand.data_ptr(), out.dist.data_ptr(), out.second.data_ptr(),
                             out.call.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
     _check(code, "snap_align")
+    return out
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().snap_align_noalloc_scratch_bytes())
+
+
+def align_noalloc(index: Index, reads, lengths, d_max: int, params: Params, out: Alignment, stream=None) -> Alignment:
+    """snap_align_noalloc: snap_align on the library's fixed per-device scratch array (no
+    workspace, no device allocation); the caller provides the output tensors."""
+    n = int(lengths.shape[0])
+    code = lib().snap_align_noalloc(index.handle, reads.data_ptr(), lengths.data_ptr(), n, d_max,
+                                    ctypes.byref(params), out.pos.data_ptr(), out.strand.data_ptr(),
+                                    out.dist.data_ptr(), out.second.data_ptr(), out.call.data_ptr(),
+                                    _stream_ptr(stream))
+    _check(code, "snap_align_noalloc")
     return out
 
 

@@ -2198,22 +2198,32 @@ extern "C" int snap_get_tuning(snap_tuning *t) {
     return SNAP_OK;
 }
 
+namespace {
+
+// The workspace a batch is sized for: one chunk of up to CHUNK_READS reads with 24 hit
+// slots a read (a chunk shrinks to fit a smaller workspace; outputs do not change).
+size_t workspace_bytes_for(const Rule &rule, int64_t n_reads, int64_t total_bases, int32_t max_len) {
+    const int NS = seeds_for_length(rule, max_len);
+    const int64_t R = std::max<int64_t>(1, std::min<int64_t>(n_reads, CHUNK_READS));
+    return make_layout(n_reads, total_bases, NS, rule.hmax, R, R * 24).total;
+}
+
+}  // namespace
+
 extern "C" size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_reads, int64_t total_bases,
                                              int32_t max_len, int32_t d_max, const snap_params *p) {
     if (!ix || n_reads < 0 || total_bases < 0 || max_len < 0 || max_len > VERIFY_LMAX || d_max < 0 ||
         !valid_params(p))
         return 0;
-    Rule rule = make_rule(ix, d_max, p);
-    const int NS = seeds_for_length(rule, max_len);
-    const int64_t R = std::max<int64_t>(1, std::min<int64_t>(n_reads, CHUNK_READS));
-    return make_layout(n_reads, total_bases, NS, p->max_hits, R, R * 24).total;
+    return workspace_bytes_for(make_rule(ix, d_max, p), n_reads, total_bases, max_len);
 }
 
 namespace {
 
 int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads, int32_t d_max,
                const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist, int32_t *second, int8_t *call,
-               void *workspace, size_t ws_bytes, void *stream, bool batched, const snap_tuning *tuning) {
+               void *workspace, size_t ws_bytes, void *stream, bool batched, const snap_tuning *tuning,
+               bool fixed_scratch = false) {
     if (!ix || n_reads < 0 || d_max < 0 || !valid_params(p)) return SNAP_EINVAL;
     if (n_reads == 0) return SNAP_OK;
     if (!reads || !lengths || !pos || !strand || !dist || !second || !call || !workspace) return SNAP_EINVAL;
@@ -2240,8 +2250,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     while ((size_t)cape * 2 * 8 + 1024 <= (size_t)lds_max) cape *= 2;
 
     // read offsets, total bases and longest read (one wait for two scalars)
+    const int too_small = fixed_scratch ? SNAP_ETOOBIG : SNAP_ENOMEM;
     Layout l0 = make_layout(n_reads, 0, 1, 1, 1, 0);
-    if (ws_bytes < l0.chunk_base + 4096) return SNAP_ENOMEM;
+    if (ws_bytes < l0.chunk_base + 4096) return too_small;
     char *ws = (char *)workspace;
     int64_t *roff = (int64_t *)(ws + l0.off_roff);
     // until the layout is known (it needs the total), two scalars live at the tail
@@ -2249,7 +2260,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     {
         size_t tb = scan_tmp_bytes(n_reads + 1);
         size_t scan_at = align256(l0.off_roff + sizeof(int64_t) * (size_t)(n_reads + 1));
-        if (scan_at + tb > ((ws_bytes - 64) & ~(size_t)255)) return SNAP_ENOMEM;
+        if (scan_at + tb > ((ws_bytes - 64) & ~(size_t)255)) return too_small;
         CastLen f{lengths, n_reads};
         HIP_OK(scan_excl(ws + scan_at, tb, f, n_reads + 1, roff, st));
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)tmp_scalars, 2, 0u);
@@ -2266,6 +2277,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     const int NS = std::max(1, seeds_for_length(rule, maxL));
     const int Kmax = dmax_for_length(rule, maxL) + rule.c - 1;
     if (Kmax > VERIFY_KMAX || maxL > VERIFY_LMAX) return SNAP_EINVAL;
+    // the fixed scratch takes exactly the batches snap_align_workspace_bytes sizes within it
+    if (fixed_scratch && workspace_bytes_for(rule, n_reads, B, maxL) > ws_bytes) return SNAP_ETOOBIG;
 
     // chunk size and pool from the workspace
     int64_t R = std::min<int64_t>(n_reads, tune.chunk_reads > 0 ? tune.chunk_reads : CHUNK_READS);
@@ -2288,7 +2301,10 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     // with room for the hits of a typical chunk: one worker's host waits and small
     // kernels then overlap the other's work
     int workers = 1;
-    const int max_workers = std::min<int64_t>(tune.workers > 0 ? tune.workers : 2, (n_reads + R - 1) / R);
+    // the fixed-scratch form runs one worker: the others' streams come from a pool that
+    // may have to create them
+    const int max_workers = fixed_scratch ? 1 : std::min<int64_t>(tune.workers > 0 ? tune.workers : 2,
+                                                                  (n_reads + R - 1) / R);
     for (int w = std::min(max_workers, MAX_WORKERS); w >= 2; w--) {
         Layout lw = make_layout(n_reads, B, NS, rule.hmax, R, 0, w);
         if (lw.total > ws_bytes) continue;
@@ -2814,6 +2830,50 @@ extern "C" int snap_align_batched(const snap_index *ix, const uint8_t *reads, co
                                   size_t ws_bytes, void *stream) {
     return align_impl(ix, reads, lengths, n_reads, d_max, p, pos, strand, dist, second, call, workspace, ws_bytes,
                       stream, true, tuning);
+}
+
+// Scratch of snap_align_noalloc: one array per device, part of the code object (placed
+// in device memory when the library is loaded on a device, held until the process
+// ends). Host code reaches it only through the address hipGetSymbolAddress gives on
+// each device; the array's name is not a device address in host code.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+__device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of the current device's scratch array, looked up once per device
+// (with that device current) and kept.
+int scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return SNAP_EDEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SNAP_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SNAP_OK;
+}
+
+}  // namespace
+
+extern "C" size_t snap_align_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+extern "C" int snap_align_noalloc(const snap_index *ix, const uint8_t *reads, const int32_t *lengths, int64_t n_reads,
+                                  int32_t d_max, const snap_params *p, int64_t *pos, int8_t *strand, int32_t *dist,
+                                  int32_t *second, int8_t *call, void *stream) {
+    if (!ix || n_reads < 0 || d_max < 0 || !valid_params(p)) return SNAP_EINVAL;
+    if (n_reads == 0) return SNAP_OK;
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != SNAP_OK) return rc;
+    return align_impl(ix, reads, lengths, n_reads, d_max, p, pos, strand, dist, second, call, ws,
+                      NOALLOC_SCRATCH_BYTES, stream, false, nullptr, true);
 }
 
 // Seed offsets tried for a read of length L (host evaluation of the same

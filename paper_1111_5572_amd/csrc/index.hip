@@ -353,6 +353,7 @@ extern "C" const char *snap_strerror(int code) {
         case SNAP_EBUSY: return "queue full";
         case SNAP_EAGAIN: return "not complete yet";
         case SNAP_EINTERNAL: return "internal consistency bound exceeded";
+        case SNAP_ETOOBIG: return "batch needs more scratch than the fixed scratch array holds";
         default: return "unknown status";
     }
 }
