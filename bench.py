@@ -146,14 +146,21 @@ def bench_index(args, w):
                       "sizes": sizes, "windows_per_s": round(sizes["windows"] / mean)}), flush=True)
 
 
-def roofline_of(kern, ctr, prefer=None):
-    """Roofline entry of the dominant kernel (or `prefer` if given)."""
+def roofline_of(kern, ctr, prefer=None, method=None):
+    """Roofline entry of the dominant kernel (or `prefer` if given).
+
+    For a verify kernel the work is Algorithm 1's own diagonal extensions when `method`
+    (the oracle's count per read on a sample of the batch, each call at its own limit)
+    is given: the batch's total, reads x extensions per read, shared among the verify
+    kernels in proportion to the extensions each ran. The extensions the kernel ran
+    (speculative ones included) give `achieved_executed` beside it."""
     if prefer is not None and prefer not in kern:
         return None
     dom = prefer if prefer in kern else max(kern.items(), key=lambda kv: kv[1][1])[0]
     launches, total_ms = kern[dom]
     avg_s = total_ms / 1000.0 / launches
     per_launch = 1.0 / launches
+    extra = {}
     if dom == "probe":
         bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
         work = ctr["seed_slots"] * PROBE_BYTES_PER_SLOT * per_launch / 1e9
@@ -169,25 +176,47 @@ def roofline_of(kern, ctr, prefer=None):
         bound, unit, peak = "alu", "TOP/s", VALU_PEAK_TOPS
         first = ctr.get("lv_steps_first", 0)
         if dom in ("verify", "verify_steal"):
-            steps = first
+            ran = first
         else:
             req = [k for k in kern if k.startswith("verify") and k not in ("verify", "verify_steal")]
             vt = sum(kern[k][1] for k in req)
-            steps = (ctr["lv_steps"] - first) * (total_ms / vt if vt > 0 else 1.0)
-        work = steps * VERIFY_OPS_PER_STEP * per_launch / 1e12
+            ran = (ctr["lv_steps"] - first) * (total_ms / vt if vt > 0 else 1.0)
+        executed = ran * VERIFY_OPS_PER_STEP * per_launch / 1e12
+        extra = {"ops_per_extension": VERIFY_OPS_PER_STEP,
+                 "achieved_executed": round(executed / avg_s, 3),
+                 "frac_executed": round(executed / avg_s / peak, 5),
+                 "extensions_per_read_executed": round(ctr["lv_steps"] / max(ctr["reads"], 1), 2)}
+        if method:
+            own = method["lv_extensions_per_read"] * ctr["reads"] * (ran / max(ctr["lv_steps"], 1))
+            work = own * VERIFY_OPS_PER_STEP * per_launch / 1e12
+            extra["work"] = "Algorithm 1's own diagonal extensions (oracle sample, each call at its own limit)"
+            extra["extensions_per_read_method"] = method["lv_extensions_per_read"]
+        else:
+            work = executed
+            extra["work"] = "diagonal extensions the kernel ran (no oracle sample in this run)"
     else:
         bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
         work = float("nan")
     achieved = work / avg_s
     return {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 5), "avg_launch_ms": round(total_ms / launches, 4), "launches": launches}
+            "frac": round(achieved / peak, 5), "avg_launch_ms": round(total_ms / launches, 4), "launches": launches,
+            **extra}
 
 
-def phases_of(kern, ctr):
-    """Roofline entries of the gather phase (HBM) and of the longest verify kernel (VALU)."""
+def phases_of(kern, ctr, method=None):
+    """Roofline entries of the gather phase (HBM), of the longest verify kernel (VALU), and
+    of every verify kernel together against Algorithm 1's own extensions."""
     ver = [k for k in kern if k.startswith("verify")]
     vdom = max(ver, key=lambda k: kern[k][1]) if ver else None
-    return {"gather": roofline_of(kern, ctr, "gather"), "verify": roofline_of(kern, ctr, vdom) if vdom else None}
+    out = {"gather": roofline_of(kern, ctr, "gather"),
+           "verify": roofline_of(kern, ctr, vdom, method) if vdom else None}
+    if ver and method:
+        vms = sum(kern[k][1] for k in ver)
+        ops = method["lv_extensions_per_read"] * ctr["reads"] * VERIFY_OPS_PER_STEP / 1e12
+        out["verify_all"] = {"bound": "alu", "kernels": ver, "ms": round(vms, 3),
+                             "achieved": round(ops / (vms / 1e3), 3), "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                             "frac": round(ops / (vms / 1e3) / VALU_PEAK_TOPS, 5)}
+    return out
 
 
 def kernel_source_sha1():
@@ -224,39 +253,70 @@ def read_traffic(path, kernel, workload, schedule):
     return None
 
 
-def cpu_baseline(g, reads, w, got, seconds, log_fn=None):
-    """The oracle on a seeded sample sized to about `seconds` of CPU time; checks
-    the GPU outputs of the sample bit-exact first."""
+def oracle_threads():
+    """Host threads for the oracle: the host cores, at most 16 (one GPU's share of a box)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def oracle_check(g, reads, w, got, seconds, single_seconds=4.0):
+    """The oracle on a seeded sample of the batch sized to about `seconds` on the host
+    cores: the GPU outputs of the sample must equal it on all five fields (else the run
+    stops with an error). Returns (cpu_baseline entry, Algorithm 1's own work per read on
+    the sample: scored locations and diagonal extensions at each call's own limit)."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = oracle_threads()
     t = time.time()
-    oix = oracle.Index(g, w.params.seed_len)
-    log(f"oracle index in {time.time() - t:.1f}s")
+    oix = oracle.Index(g, w.params.seed_len, threads=threads)
+    log(f"oracle index in {time.time() - t:.1f}s ({threads} threads)")
     op = oracle.params_from(w.params)
     rng = np.random.default_rng(7)
-    probe_n = min(reads.n, 2000)
-    idx = np.sort(rng.choice(reads.n, probe_n, replace=False))
-    sub = reads.subset(idx)
-    t = time.perf_counter()
-    res = oix.align_reads(sub, op, threads=threads)
-    dt = time.perf_counter() - t
-    rate = probe_n / max(dt, 1e-9)
-    n_s = int(min(reads.n, max(probe_n, rate * seconds)))
-    if n_s > probe_n:
-        idx = np.sort(rng.choice(reads.n, n_s, replace=False))
+
+    def sample(k):
+        return np.unique(rng.integers(0, reads.n, size=min(k, reads.n)))
+
+    def run(idx, nthreads):
         sub = reads.subset(idx)
-        t = time.perf_counter()
-        res = oix.align_reads(sub, op, threads=threads)
-        dt = time.perf_counter() - t
+        t0 = time.perf_counter()
+        res = oix.align_reads(sub, op, threads=nthreads)
+        return res, time.perf_counter() - t0
+
+    # one thread on a small sample (the paper quotes one core's rate)
+    idx1 = sample(500)
+    res1, dt1 = run(idx1, 1)
+    n1 = int(min(reads.n, max(len(idx1), len(idx1) / max(dt1, 1e-9) * single_seconds)))
+    if n1 > len(idx1):
+        idx1 = sample(n1)
+        res1, dt1 = run(idx1, 1)
+    single = round(len(idx1) / dt1, 1)
+    # all threads, sized from a probe
+    idx = sample(4000)
+    res, dt = run(idx, threads)
+    n_s = int(min(reads.n, max(len(idx), len(idx) / max(dt, 1e-9) * seconds)))
+    if n_s > len(idx):
+        idx = sample(n_s)
+        res, dt = run(idx, threads)
     oix.close()
-    mism = sum(int(np.count_nonzero(np.asarray(a)[idx].astype(np.int64) != np.asarray(b).astype(np.int64)))
-               for a, b in zip(got, res.fields()))
+    checked = [(idx, res), (idx1, res1)]
+    mism = 0
+    for ix_, r_ in checked:
+        mism += sum(int(np.count_nonzero(np.asarray(a)[ix_].astype(np.int64) != np.asarray(b).astype(np.int64)))
+                    for a, b in zip(got, r_.fields()))
     if mism:
         print(json.dumps({"error": f"GPU output differs from the oracle on {mism} fields of the sample"}), flush=True)
         sys.exit(1)
-    return {"value": round(len(idx) / dt, 1), "unit": "reads/s", "cores": res.threads, "kind": "oracle",
-            "sample": f"{len(idx)} seeded-random reads of the {w.name} workload, {dt:.1f}s, "
-                      f"bit-exact vs GPU on all five outputs"}
+    st = res.stats
+    method = {"reads": len(idx), "ed_calls_per_read": round(st["ed_calls"] / len(idx), 3),
+              "lv_extensions_per_read": round(st["lv_extensions"] / len(idx), 2),
+              "seeds_looked_up_per_read": round(st["seeds_looked_up"] / len(idx), 3),
+              "candidates_per_read": round(st["candidates"] / len(idx), 2)}
+    cpu = {"value": round(len(idx) / dt, 1), "unit": "reads/s", "cores": res.threads, "kind": "oracle",
+           "single_thread_value": single,
+           "sample": f"{len(idx)} seeded-random reads of the {w.name} workload on {res.threads} threads "
+                     f"({dt:.1f}s) and {len(idx1)} on one thread ({dt1:.1f}s), each bit-exact vs GPU on all "
+                     f"five outputs; the oracle is plain, not a tuned CPU aligner"}
+    log(f"cpu baseline: {cpu}")
+    log(f"Algorithm 1's own work on the sample: {method}")
+    return cpu, method
 
 
 LENGTH_BUCKETS = [(0, 300), (301, 1000), (1001, 3000), (3001, 1 << 30)]
@@ -362,9 +422,9 @@ def bench_batched(args, w, dev):
     if not same:
         print(json.dumps({"error": "batched and per-bucket plain outputs differ"}), flush=True)
         sys.exit(1)
-    roofline = roofline_of(kern, ctr)
+    cpu, method = (None, None) if args.no_cpu_baseline else oracle_check(g, reads, w, got, args.cpu_seconds)
+    roofline = roofline_of(kern, ctr, method=method)
     roofline["traffic"] = None
-    cpu = None if args.no_cpu_baseline else cpu_baseline(g, reads, w, got, args.cpu_seconds)
     calls = np.bincount(got[4].astype(np.int64), minlength=3)
     line = {
         "metric": "reads aligned/s", "value": round(reads.n / batched_s, 1), "unit": "reads/s",
@@ -387,8 +447,9 @@ def bench_batched(args, w, dev):
         "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
         "roofline": roofline,
         # the two phases the method hinges on: gather (HBM-bound) and verify (VALU-bound)
-        "phases": phases_of(kern, ctr),
+        "phases": phases_of(kern, ctr, method),
         "cpu_baseline": cpu,
+        "method_work": method,
     }
     print(json.dumps(line), flush=True)
     gix.close()
@@ -512,12 +573,224 @@ def bench_served(args, w, dev):
     print(json.dumps(line), flush=True)
 
 
+def streamed_steps(gix, reads, w, params, got, chunks, steps, dev):
+    """The batch aligned from pinned host memory: the reads go to the device in `chunks`
+    parts (one stream copies part k+1 in while part k is aligned on another; two device
+    buffers alternate) and each part's outputs come back on a third stream as soon as it
+    is aligned. Timed from the first host-to-device copy to the last device-to-host copy
+    (index resident). Outputs must equal the resident run's."""
+    import torch
+    import paper_1111_5572_amd as snapgpu
+    n = reads.n
+    offs = reads.offsets
+    rb = np.linspace(0, n, chunks + 1).astype(np.int64)
+    t = time.time()
+    hb = torch.empty(int(reads.bases.shape[0]), dtype=torch.uint8, pin_memory=True)
+    hb.numpy()[:] = reads.bases
+    hl = torch.empty(n, dtype=torch.int32, pin_memory=True)
+    hl.numpy()[:] = reads.lengths
+    host_out = [torch.empty(n, dtype=dt, pin_memory=True)
+                for dt in (torch.int64, torch.int8, torch.int32, torch.int32, torch.int8)]
+    log(f"streamed: {hb.numel() / 1e9:.1f} GB of reads in pinned host memory ({time.time() - t:.1f}s)")
+    max_b = int(max(offs[rb[k + 1]] - offs[rb[k]] for k in range(chunks)))
+    max_r = int(max(rb[k + 1] - rb[k] for k in range(chunks)))
+    ml = int(reads.lengths.max())
+    dbuf = [torch.empty(max_b, dtype=torch.uint8, device=dev) for _ in range(2)]
+    dlen = [torch.empty(max_r, dtype=torch.int32, device=dev) for _ in range(2)]
+    out = snapgpu.Alignment(*(torch.empty(n, dtype=t_.dtype, device=dev) for t_ in host_out))
+    wb = 4 * snapgpu.workspace_bytes(gix, max_r, max_b, ml, w.params.d_max, params)
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    s_in, s_out = torch.cuda.Stream(), torch.cuda.Stream()
+    s_c = torch.cuda.current_stream()
+
+    def h2d(k, ev_done):
+        b = k % 2
+        r0, r1 = int(rb[k]), int(rb[k + 1])
+        o0, o1 = int(offs[r0]), int(offs[r1])
+        with torch.cuda.stream(s_in):
+            if k >= 2:
+                s_in.wait_event(ev_done[k - 2])   # the buffer's previous part is aligned
+            dbuf[b][:o1 - o0].copy_(hb[o0:o1], non_blocking=True)
+            dlen[b][:r1 - r0].copy_(hl[r0:r1], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s_in)
+        return ev
+
+    def one_step():
+        ev_in = [None] * chunks
+        ev_done = [None] * chunks
+        ev_in[0] = h2d(0, ev_done)
+        for k in range(chunks):
+            if k + 1 < chunks:
+                ev_in[k + 1] = h2d(k + 1, ev_done)
+            b = k % 2
+            r0, r1 = int(rb[k]), int(rb[k + 1])
+            o0, o1 = int(offs[r0]), int(offs[r1])
+            s_c.wait_event(ev_in[k])
+            part = snapgpu.Alignment(*(t_[r0:r1] for t_ in (out.pos, out.strand, out.dist, out.second, out.call)))
+            snapgpu.align(gix, dbuf[b][:o1 - o0], dlen[b][:r1 - r0], w.params.d_max, params, out=part,
+                          workspace=ws, stream=s_c, max_len=ml)
+            ev_done[k] = torch.cuda.Event()
+            ev_done[k].record(s_c)
+            with torch.cuda.stream(s_out):
+                s_out.wait_event(ev_done[k])
+                for h, d in zip(host_out, (part.pos, part.strand, part.dist, part.second, part.call)):
+                    h[r0:r1].copy_(d, non_blocking=True)
+        torch.cuda.synchronize()
+
+    one_step()   # untimed
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one_step()
+        times.append(time.perf_counter() - t0)
+    same = all(np.array_equal(h.numpy().astype(np.int64), np.asarray(g_).astype(np.int64))
+               for h, g_ in zip(host_out, got))
+    if not same:
+        print(json.dumps({"error": "outputs aligned from host memory differ from the resident run's"}), flush=True)
+        sys.exit(1)
+    sec = sum(times) / len(times)
+    res = {"reads_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1000, 3), "steps": steps,
+           "chunks": chunks, "host_bytes_in": int(hb.numel() + 4 * n), "host_bytes_out": int(18 * n),
+           "outputs_equal_resident": True}
+    log(f"streamed from host memory: {res}")
+    del hb, hl, host_out, dbuf, dlen, out, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_plain(args, w, dev):
+    """One step = snap_align over the whole batch (reads and index resident in HBM)."""
+    import torch
+    import paper_1111_5572_amd as snapgpu
+
+    t = time.time()
+    g = w.make_genome()
+    log(f"genome {w.name}: {len(g)} bases in {time.time() - t:.1f}s")
+    t = time.time()
+    reads = w.make_reads(g)
+    log(f"reads: {reads.n} ({int(reads.bases.shape[0])} bases) in {time.time() - t:.1f}s")
+    t = time.time()
+    gix = build_index(g, w.params.seed_len)
+    index_s = time.time() - t
+    sizes = gix.sizes()
+    log(f"index built and resident in {index_s:.1f}s: {sizes}")
+
+    rb = torch.from_numpy(reads.bases).to(dev)
+    ln = torch.from_numpy(reads.lengths).to(dev)
+    params = snapgpu.params_from(w.params)
+    max_len = int(reads.lengths.max())
+    # a generous workspace: more reads per internal pass, fewer waits (outputs do not change)
+    wb = 4 * snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), max_len, w.params.d_max, params)
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    tune_info = None
+    if args.tuning:
+        snapgpu.set_tuning(*[int(x) for x in args.tuning.split(",")])
+        log(f"fixed schedule {snapgpu.get_tuning()}")
+    elif not args.no_autotune:
+        from paper_1111_5572_amd import autotune
+        rec = None if args.retune else autotune.lookup_entry(reads.lengths, batched=False)
+        if rec:
+            tune_info = dict(rec, source="tuning table")
+        else:
+            tune_info = autotune.tune(gix, rb, ln, w.params.d_max, params, batched=False,
+                                      sample_reads=min(reads.n, 1_000_000), table_path=args.tuning_out or None,
+                                      log=log)
+            tune_info["workload"] = f"{w.name} ({w.notes}), MI355X"
+        snapgpu.set_tuning(*tune_info["tuning"])
+        log(f"schedule {tuple(tune_info['tuning'])} ({tune_info.get('source', 'autotuned')})")
+    out = snapgpu.align(gix, rb, ln, w.params.d_max, params, workspace=ws, max_len=max_len)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, max_len=max_len)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    # timed steps, nothing else on: reads resident in HBM when the clock starts
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, stream=stream, max_len=max_len)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    reads_per_s = reads.n * args.steps / elapsed
+    gbases_per_s = float(reads.bases.shape[0]) * args.steps / elapsed / 1e9
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {reads_per_s:,.0f} reads/s")
+
+    # profiled steps of their own: per-kernel times (an event pair on each launch's
+    # stream) and device counters
+    prof_steps = max(1, min(args.steps, 2))
+    snapgpu.profile_begin()
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(prof_steps):
+        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, stream=stream, max_len=max_len)
+    torch.cuda.synchronize()
+    prof_ms = 1000.0 * (time.perf_counter() - tp) / prof_steps
+    kern = snapgpu.profile_end()
+    ctr = snapgpu.profile_counters()
+    log(f"profiled {prof_steps} steps: {prof_ms:.2f} ms/step")
+    log("kernels: " + ", ".join(f"{k} {v[1] / max(v[0], 1):.3f} ms x{v[0]}" for k, v in kern.items()))
+    log(f"counters: {ctr}")
+
+    got = out.numpy()
+    calls = np.bincount(got[4].astype(np.int64), minlength=3)
+    del ws
+    torch.cuda.empty_cache()
+    streamed = None
+    if args.stream_chunks > 0:
+        del rb
+        torch.cuda.empty_cache()
+        streamed = streamed_steps(gix, reads, w, params, got, args.stream_chunks, max(1, min(args.steps, 2)), dev)
+
+    # CPU oracle on a bounded sample: bit-exact check, baseline rate, Algorithm 1's own work
+    cpu, method = (None, None) if args.no_cpu_baseline else oracle_check(g, reads, w, got, args.cpu_seconds)
+
+    # roofline of the dominant kernel, with HBM traffic from the committed counter summary
+    roofline = roofline_of(kern, ctr, method=method)
+    roofline["traffic"] = read_traffic(args.traffic, roofline["kernel"], w.name, snapgpu.get_tuning())
+
+    line = {
+        "metric": "reads aligned/s", "value": round(reads_per_s, 1), "unit": "reads/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded genome and simulated reads; no real data)",
+        "config": {"workload": w.name, "genome_bases": len(g), "reads": reads.n,
+                   "read_len": (int(reads.lengths.max()) if reads.lengths.min() == reads.lengths.max()
+                                else sorted({int(x) for x in np.unique(reads.lengths)[:4]})),
+                   "seed_len": w.params.seed_len,
+                   "seeds_per_read": w.params.n_min, "d_max": w.params.d_max, "conf_c": w.params.conf_c,
+                   "max_hits": w.params.max_hits},
+        "gbases_per_s": round(gbases_per_s, 4),
+        "timed_region": "reads and index resident in HBM; no profiling in the timed steps",
+        "with_host_copies": streamed,
+        "index_build_s": round(index_s, 2), "index_build": "host" if INDEX_ON_HOST else "device",
+        "index_device_bytes": sizes["device_bytes"],
+        "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
+        "profiled_ms_per_step": round(prof_ms, 3),
+        "kernel_ms_per_step": {k: round(v[1] / prof_steps, 4) for k, v in kern.items()},
+        "counters_per_step": {k: v // prof_steps for k, v in ctr.items()},
+        "schedule": tune_info,
+        "roofline": roofline,
+        # the two phases the method hinges on: gather (HBM-bound) and verify (VALU-bound)
+        "phases": phases_of(kern, ctr, method),
+        "cpu_baseline": cpu,
+        "method_work": method,
+    }
+    print(json.dumps(line), flush=True)
+    gix.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="human")
     ap.add_argument("--reads", type=int, default=0, help="override the read count (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -532,6 +805,9 @@ def main():
                     help="time the index build of the workload's genome (--steps builds) and stop")
     ap.add_argument("--retune", action="store_true",
                     help="run the autotuner even when the package's tuning table has this length class")
+    ap.add_argument("--tuning-out", default="", help="record an autotuned schedule in this JSON table")
+    ap.add_argument("--stream-chunks", type=int, default=8,
+                    help="also time the batch aligned from pinned host memory in this many parts (0: skip)")
     ap.add_argument("--tuning", default="", help="fixed schedule a,b,c,d (snap_tuning fields); skips the autotuner")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's plain copy kernel over this many bytes, 3 times "
@@ -572,132 +848,7 @@ def main():
     if args.workload == "served":
         return bench_served(args, w, dev)
 
-    t = time.time()
-    g = w.make_genome()
-    log(f"genome {w.name}: {len(g)} bases in {time.time() - t:.1f}s")
-    t = time.time()
-    reads = w.make_reads(g)
-    log(f"reads: {reads.n} ({int(reads.bases.shape[0])} bases) in {time.time() - t:.1f}s")
-    t = time.time()
-    gix = build_index(g, w.params.seed_len)
-    index_s = time.time() - t
-    sizes = gix.sizes()
-    log(f"index built and resident in {index_s:.1f}s: {sizes}")
-
-    rb = torch.from_numpy(reads.bases).to(dev)
-    ln = torch.from_numpy(reads.lengths).to(dev)
-    params = snapgpu.params_from(w.params)
-    max_len = int(reads.lengths.max())
-    # a generous workspace: more reads per internal pass, fewer waits (outputs do not change)
-    wb = 4 * snapgpu.workspace_bytes(gix, reads.n, int(reads.bases.shape[0]), max_len, w.params.d_max, params)
-    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
-    tune_info = None
-    if args.tuning:
-        snapgpu.set_tuning(*[int(x) for x in args.tuning.split(",")])
-        log(f"fixed schedule {snapgpu.get_tuning()}")
-    elif not args.no_autotune:
-        from paper_1111_5572_amd import autotune
-        rec = None if args.retune else autotune.lookup_entry(reads.lengths, batched=False)
-        if rec:
-            tune_info = dict(rec, source="tuning table")
-        else:
-            tune_info = autotune.tune(gix, rb, ln, w.params.d_max, params, batched=False,
-                                      sample_reads=min(reads.n, 1_000_000), table_path=None, log=log)
-        snapgpu.set_tuning(*tune_info["tuning"])
-        log(f"schedule {tuple(tune_info['tuning'])} ({tune_info.get('source', 'autotuned')})")
-    out = snapgpu.align(gix, rb, ln, w.params.d_max, params, workspace=ws, max_len=max_len)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, max_len=max_len)
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
-
-    snapgpu.profile_begin()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, stream=stream, max_len=max_len)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern = snapgpu.profile_end()
-    ctr = snapgpu.profile_counters()
-    elapsed = t1 - t0
-    ms_per_step = 1000.0 * elapsed / args.steps
-    reads_per_s = reads.n * args.steps / elapsed
-    gbases_per_s = float(reads.bases.shape[0]) * args.steps / elapsed / 1e9
-    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {reads_per_s:,.0f} reads/s")
-    log("kernels: " + ", ".join(f"{k} {v[1] / max(v[0], 1):.3f} ms x{v[0]}" for k, v in kern.items()))
-    log(f"counters: {ctr}")
-
-    got = out.numpy()
-    calls = np.bincount(got[4].astype(np.int64), minlength=3)
-
-    # roofline of the dominant kernel, with HBM traffic from the committed counter summary
-    roofline = roofline_of(kern, ctr)
-    roofline["traffic"] = read_traffic(args.traffic, roofline["kernel"], w.name, snapgpu.get_tuning())
-
-    # CPU oracle on a bounded sample, and a bit-exact check of that sample
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
-        t = time.time()
-        oix = oracle.Index(g, w.params.seed_len)
-        log(f"oracle index in {time.time() - t:.1f}s")
-        op = oracle.params_from(w.params)
-        rng = np.random.default_rng(7)
-        probe_n = min(reads.n, 4000)
-        idx = np.sort(rng.choice(reads.n, probe_n, replace=False))
-        sub = reads.subset(idx)
-        t = time.perf_counter()
-        res = oix.align_reads(sub, op, threads=threads)
-        dt = time.perf_counter() - t
-        rate = probe_n / max(dt, 1e-9)
-        n_s = int(min(reads.n, max(probe_n, rate * args.cpu_seconds)))
-        if n_s > probe_n:
-            idx = np.sort(rng.choice(reads.n, n_s, replace=False))
-            sub = reads.subset(idx)
-            t = time.perf_counter()
-            res = oix.align_reads(sub, op, threads=threads)
-            dt = time.perf_counter() - t
-        oix.close()
-        mism = sum(int(np.count_nonzero(np.asarray(a)[idx].astype(np.int64) != np.asarray(b).astype(np.int64)))
-                   for a, b in zip(got, res.fields()))
-        if mism:
-            print(json.dumps({"error": f"GPU output differs from the oracle on {mism} fields of the sample"}), flush=True)
-            sys.exit(1)
-        cpu = {"value": round(len(idx) / dt, 1), "unit": "reads/s", "cores": res.threads, "kind": "oracle",
-               "sample": f"{len(idx)} seeded-random reads of the {w.name} workload, {dt:.1f}s, "
-                         f"bit-exact vs GPU on all five outputs"}
-        log(f"cpu baseline: {cpu}")
-
-    line = {
-        "metric": "reads aligned/s", "value": round(reads_per_s, 1), "unit": "reads/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic (seeded genome and simulated reads; no real data)",
-        "config": {"workload": w.name, "genome_bases": len(g), "reads": reads.n,
-                   "read_len": (int(reads.lengths.max()) if reads.lengths.min() == reads.lengths.max()
-                                else f"{int(reads.lengths.min())}-{int(reads.lengths.max())}"),
-                   "seed_len": w.params.seed_len,
-                   "seeds_per_read": w.params.n_min, "d_max": w.params.d_max, "conf_c": w.params.conf_c,
-                   "max_hits": w.params.max_hits},
-        "gbases_per_s": round(gbases_per_s, 4),
-        "index_build_s": round(index_s, 2), "index_build": "host" if INDEX_ON_HOST else "device",
-        "index_device_bytes": sizes["device_bytes"],
-        "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
-        "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
-        "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
-        "schedule": tune_info,
-        "roofline": roofline,
-        # the two phases the method hinges on: gather (HBM-bound) and verify (VALU-bound)
-        "phases": phases_of(kern, ctr),
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
-    gix.close()
+    return bench_plain(args, w, dev)
 
 
 if __name__ == "__main__":

@@ -36,6 +36,15 @@ CANDIDATES = [
     (5, 8, 8, 0, 1, 3),
     (6, 5, 5, 0, 1, 0),
     (5, 5, 5, 256, 1, 0),
+    # larger limits and more exact rounds, for longer reads and larger d_max
+    (5, 6, 6, 0, 2, 0),
+    (5, 6, 6, 0, 3, 0),
+    (5, 8, 8, 0, 1, 0),
+    (5, 8, 8, 0, 2, 0),
+    (5, 10, 10, 0, 2, 0),
+    (4, 6, 6, 0, 2, 0),
+    (6, 8, 8, 0, 2, 0),
+    (5, 4, 4, 0, 2, 0),
 ]
 
 

@@ -48,7 +48,8 @@ def test_traffic_needs_matching_kernel_source(bench, tmp_path):
 def test_roofline_first_verification_counted_alone(bench):
     # ms totals per kernel over 10 launches each; 1e9 steps in all, 6e8 of them first-verification
     kern = {"verify": (10, 20.0), "verify_request": (10, 5.0), "verify_request_wave": (10, 15.0), "probe": (10, 4.0)}
-    ctr = {"lv_steps": 1_000_000_000, "lv_steps_first": 600_000_000, "seed_slots": 0, "hits": 0, "locations": 0}
+    ctr = {"lv_steps": 1_000_000_000, "lv_steps_first": 600_000_000, "seed_slots": 0, "hits": 0, "locations": 0,
+           "reads": 1_000_000}
     r = bench.roofline_of(kern, ctr, "verify")
     # 6e8 steps x 30 ops / 10 launches / 2 ms a launch
     assert r["achieved"] == pytest.approx(6e8 * 30 / 10 / 2e-3 / 1e12, rel=1e-4)
@@ -58,6 +59,24 @@ def test_roofline_first_verification_counted_alone(bench):
     assert q["achieved"] == pytest.approx(4e8 * 0.25 * 30 / 10 / 0.5e-3 / 1e12, rel=1e-4)
     assert bench.roofline_of(kern, ctr, "absent") is None
     assert bench.roofline_of(kern, ctr)["kernel"] == "verify"   # the largest total
+    assert r["extensions_per_read_executed"] == 1000
+
+
+def test_roofline_counts_algorithm1_own_extensions(bench):
+    # the method needs 100 extensions a read (oracle sample); the kernels ran 1000 a read:
+    # 60% of them in the first verification, which is credited with 60% of the method's
+    kern = {"verify": (10, 20.0), "verify_request": (10, 5.0), "verify_request_wave": (10, 15.0)}
+    ctr = {"lv_steps": 1_000_000_000, "lv_steps_first": 600_000_000, "seed_slots": 0, "hits": 0, "locations": 0,
+           "reads": 1_000_000}
+    method = {"lv_extensions_per_read": 100.0}
+    r = bench.roofline_of(kern, ctr, "verify", method)
+    assert r["achieved"] == pytest.approx(1e8 * 0.6 * 30 / 10 / 2e-3 / 1e12, rel=1e-4)
+    assert r["achieved_executed"] == pytest.approx(6e8 * 30 / 10 / 2e-3 / 1e12, rel=1e-3)
+    assert r["extensions_per_read_method"] == 100.0
+    ph = bench.phases_of(kern, ctr, method)
+    # every verify kernel together: 1e8 extensions x 30 ops over 40 ms
+    assert ph["verify_all"]["achieved"] == pytest.approx(1e8 * 30 / 40e-3 / 1e12, rel=1e-3)
+    assert ph["verify"]["kernel"] == "verify"
 
 
 def test_accuracy_metrics(bench):
