@@ -47,8 +47,8 @@ typedef struct snap_index snap_index;
 typedef struct {
     uint64_t genome_len;      /* G, bases */
     int32_t seed_len;         /* s */
-    int32_t reserved;
-    uint64_t windows;         /* N-free windows of length s (index entries per orientation) */
+    int32_t stride;           /* windows at positions that are multiples of it are indexed (1: all) */
+    uint64_t windows;         /* indexed N-free windows of length s (entries per orientation) */
     uint64_t distinct_keys;   /* distinct seeds up to reverse complement */
     uint64_t table_slots;     /* slots of the open-addressing seed table (8 per 128-byte bucket) */
     uint64_t position_entries;/* entries of the position array (windows + palindromic windows) */
@@ -94,6 +94,20 @@ int snap_index_build_progress(const uint8_t *genome, uint64_t len, int32_t seed_
  * or len >= 2^32), SNAP_ENOMEM, SNAP_EDEVICE. On error *out is NULL. */
 int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_len, void *stream,
                             snap_progress_fn progress, void *ctx, snap_index **out);
+
+/* The strided index of Section 3.1's footnote to overlapping seeds: the same device build,
+ * but only the windows at positions that are multiples of `stride` (1, 2 or 4) are indexed,
+ * so the positions array and the table shrink by about that factor. snap_align with such an
+ * index looks up, for each seed slot at read offset o, the `stride` seeds at o, o + 1, ...,
+ * o + stride - 1 that fit in the read (one of them starts at an indexed position of any
+ * location): the slot is skipped as holding an N when any of those bases is an N, its entries
+ * for the h_max test are the sum over its seeds, it votes once for every location any of its
+ * seeds hit, and it counts as a non-overlapping seed of Algorithm 1 only when it is at a
+ * multiple of s and all its `stride` seeds fit. stride 1 is snap_index_build_device.
+ * Reads align with seeds-per-read times stride of at most 64 (SNAP_EINVAL otherwise).
+ * Errors: as snap_index_build_device, and SNAP_EINVAL for any other stride. */
+int snap_index_build_strided(const uint8_t *genome, uint64_t len, int32_t seed_len, int32_t stride, void *stream,
+                             snap_progress_fn progress, void *ctx, snap_index **out);
 
 /* Release the index and its device memory. NULL is accepted. */
 int snap_index_free(snap_index *ix);
@@ -208,10 +222,10 @@ int32_t snap_max_limit(void);
  * limit pass1_limit; the final pass probes every seed slot of the reads left over
  * and verifies with limit final_limit. In either pass Algorithm 1 is then replayed
  * on what was computed; where a replay needs a distance above the limit a location
- * was verified with, the read's undecided locations are verified again with the
- * full limit d_max(L) + c - 1 (reads in the lane tile) or that location with
- * exactly the limit the replay uses (longer reads), and the read is replayed
- * again. Only reads that need more seeds than the first pass probed go on to the
+ * was verified with, that location is verified again with exactly the limit the
+ * replay uses, or (reads in the lane tile, once the limit is below d_max(L) + c - 1
+ * or after exact_rounds rounds) every unscored location still undecided at that
+ * limit, and the read is replayed again. Only reads that need more seeds than the first pass probed go on to the
  * final pass. 0 in a field means "no cap" (no first pass when pass1_seeds and
  * pass1_limit are both 0). Outputs never depend on these values.
  */
@@ -221,8 +235,8 @@ typedef struct {
     int32_t final_limit;
     int32_t lane_max_len;   /* verify tile: reads up to this length (and limits up to 63) get one lane
                                per location, longer ones a wave per location; 0 = 512 (the maximum) */
-    int32_t exact_rounds;   /* lane-tile reads ask for single locations at the exact limit in this many
-                               replay rounds, then for all their undecided locations at the full limit */
+    int32_t exact_rounds;   /* lane-tile reads ask for single locations at the full limit in at most this
+                               many replay rounds, then for all their undecided locations at the limit */
     int32_t verify_seeds;   /* snap_align, reads in the lane tile: the first verification covers only
                                locations hit by one of the first verify_seeds seed slots, the others
                                are verified when a replay asks (0 = all locations) */

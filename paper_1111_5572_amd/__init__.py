@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
 
 
 class IndexSizes(ctypes.Structure):
-    _fields_ = [("genome_len", ctypes.c_uint64), ("seed_len", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("genome_len", ctypes.c_uint64), ("seed_len", ctypes.c_int32), ("stride", ctypes.c_int32),
                 ("windows", ctypes.c_uint64), ("distinct_keys", ctypes.c_uint64),
                 ("table_slots", ctypes.c_uint64), ("position_entries", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
@@ -124,6 +124,8 @@ def lib():
         L.snap_index_build_progress.restype = ctypes.c_int
         L.snap_index_build_device.argtypes = [P, u64, i32, P, PROGRESS_FN, P, ctypes.POINTER(P)]
         L.snap_index_build_device.restype = ctypes.c_int
+        L.snap_index_build_strided.argtypes = [P, u64, i32, i32, P, PROGRESS_FN, P, ctypes.POINTER(P)]
+        L.snap_index_build_strided.restype = ctypes.c_int
         L.snap_debug_index_download.argtypes = [P, i32, P, u64]
         L.snap_debug_index_download.restype = ctypes.c_int
         L.snap_index_free.argtypes = [P]
@@ -222,10 +224,16 @@ class Index:
     with on_device=True, by device kernels on the current stream (snap_index_build_device).
     `progress`, if given, is called with the text of each finished build stage."""
 
-    def __init__(self, genome, seed_len: int = 20, progress=None, on_device: bool = False):
+    def __init__(self, genome, seed_len: int = 20, progress=None, on_device: bool = False, stride: int = 1):
         g = _np_u8(genome)
         h = ctypes.c_void_p()
-        if on_device:
+        if stride != 1:
+            import torch
+            stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+            cb = PROGRESS_FN(lambda stage, ctx: progress(stage.decode())) if progress else PROGRESS_FN()
+            _check(lib().snap_index_build_strided(g.ctypes.data, g.shape[0], seed_len, stride, stream, cb, None,
+                                                  ctypes.byref(h)), "snap_index_build_strided")
+        elif on_device:
             import torch
             stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
             cb = PROGRESS_FN(lambda stage, ctx: progress(stage.decode())) if progress else PROGRESS_FN()
@@ -239,6 +247,7 @@ class Index:
                    "snap_index_build_progress")
         self._h = h
         self.seed_len = seed_len
+        self.stride = stride
         self.genome_len = int(g.shape[0])
 
     @property

@@ -45,6 +45,10 @@ CANDIDATES = [
     (4, 6, 6, 0, 2, 0),
     (6, 8, 8, 0, 2, 0),
     (5, 4, 4, 0, 2, 0),
+    (5, 6, 6, 0, 5, 0),
+    (5, 6, 6, 0, 8, 0),
+    (5, 4, 4, 0, 5, 0),
+    (5, 8, 8, 0, 5, 0),
 ]
 
 

@@ -269,6 +269,7 @@ struct Pass {
     int32_t NS;        // seed slots probed in this pass
     int32_t Kcap;      // verify limit cap: distances above min(Kcap, K(L)) stay unknown
     int32_t final_pass;
+    int32_t ST;        // seeds per slot: the index's stride (one probe record each)
 };
 
 __device__ inline int64_t gid(const Pass &p, int64_t r) {
@@ -284,45 +285,53 @@ struct ProbeArgs {
     Pass ps;
     Rule rule;
     Shifts sh;
-    ProbeRec *out;         // nr * NS records
+    ProbeRec *out;         // nr * NS * ST records
     uint32_t *hits;        // per read: hits of its looked-up seeds (zeroed before the launch)
 };
 
-// A wave takes 64 (read, seed slot) items. First each lane computes one item's seed
-// (offset, 2s-bit code, N test, canonical code); then in 8 rounds every group of eight
-// lanes probes one item, each lane reading one 16-byte slot of the seed's 128-byte
-// bucket (one coalesced cache line per probe step); results come back to the item's
-// lane through LDS, and each lane writes its own record. A read's hits (the counts of
-// its looked-up seeds within h_max) are summed over its lanes by a segmented scan; a
-// read split between two waves adds its two parts atomically.
+// A wave takes 64 (read, seed slot, seed of the slot) items; a slot has one seed, or
+// with a strided index ST seeds at consecutive offsets (consecutive lanes). First each
+// lane computes one item's seed (offset, 2s-bit code, N test, canonical code); then in 8
+// rounds every group of eight lanes probes one item, each lane reading one 16-byte slot
+// of the seed's 128-byte bucket (one coalesced cache line per probe step); results come
+// back to the item's lane through LDS. The lanes of a slot then combine their N tests and
+// entry counts (the slot is skipped for an N in any of its seeds, over h_max on the sum),
+// and each lane writes its own record. A read's hits (the counts of its looked-up seeds
+// within h_max) are summed over its lanes by a segmented scan; a read split between two
+// waves adds its two parts atomically.
 __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
     __shared__ uint64_t res_val[4][64];
     __shared__ uint8_t res_found[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int sub = lane & 7, grp = lane >> 3;
     const int s = a.ix.s;
-    const int NS = a.ps.NS;
-    const int64_t nitems = a.ps.nr * (int64_t)NS;
+    const int NS = a.ps.NS, ST = a.ps.ST;
+    const int NI = NS * ST;                       // items per read (at most 64)
+    const int64_t nitems = a.ps.nr * (int64_t)NI;
     const int64_t item = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64 + lane;
     const bool valid = item < nitems;
-    // item = r * NS + i (32-bit division when the pass's items fit 32 bits, as they do
-    // for any chunk of up to 2^27 reads)
+    // item = r * NI + k (32-bit division when the pass's items fit 32 bits, as they do
+    // for any chunk of up to 2^26 reads); slot i = k / ST, seed j = k % ST of the slot
     int64_t r = 0;
-    int i = 0;
+    int k = 0;
     if (valid) {
         if (nitems <= 0xFFFFFFFFll) {
-            const uint32_t r32 = (uint32_t)item / (uint32_t)NS;
+            const uint32_t r32 = (uint32_t)item / (uint32_t)NI;
             r = r32;
-            i = (int)((uint32_t)item - r32 * (uint32_t)NS);
+            k = (int)((uint32_t)item - r32 * (uint32_t)NI);
         } else {
-            r = item / NS;
-            i = (int)(item - r * NS);
+            r = item / NI;
+            k = (int)(item - r * NI);
         }
     }
+    const int i = k / ST, j = k - i * ST;
     const int64_t g = valid ? gid(a.ps, r) : 0;
     const int L = valid ? a.len[g] : 0;
     int o = -1;
-    if (valid && i < seeds_for_length(a.rule, L)) o = seed_offset(a.sh, s, L, i);
+    if (valid && i < seeds_for_length(a.rule, L)) {
+        const int os = seed_offset(a.sh, s, L, i);
+        if (os >= 0 && os + j + s <= L) o = os + j;   // the slot's seed j, if it fits the read
+    }
     int status = ST_NONE;
     uint64_t key = 0, canon = 0;
     if (o >= 0) {
@@ -394,15 +403,23 @@ __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
     __builtin_amdgcn_wave_barrier();
     const bool found = valid && res_found[wv][lane] != 0;
     const uint64_t val = res_val[wv][lane];
+    const uint32_t nf = found ? (uint32_t)((val >> 36) & CNT_SAT) : 0u;
+    const uint32_t nrv = found ? (uint32_t)((val >> 50) & CNT_SAT) : 0u;
+    // the slot's entries (occ(S) + occ(RC S), summed over its seeds) and N test; a slot's
+    // ST lanes are an aligned group of the wave (64 is a multiple of ST)
+    uint32_t entries = status == ST_OK ? nf + nrv : 0u;
+    int any_n = status == ST_N ? 1 : 0;
+    for (int m = 1; m < ST; m <<= 1) {
+        entries += (uint32_t)__shfl_xor((int)entries, m, 64);
+        any_n |= __shfl_xor(any_n, m, 64);
+    }
+    if (status != ST_NONE) status = any_n ? ST_N : ((int64_t)entries > a.rule.hmax ? ST_OVER : ST_OK);
     ProbeRec rec{};
     rec.status = (uint8_t)status;
     rec.o = (uint16_t)(o < 0 ? 0 : o);
     if (status == ST_OK && found) {
         const uint64_t off = val & OFF_MASK;
-        const uint32_t nf = (uint32_t)((val >> 36) & CNT_SAT), nrv = (uint32_t)((val >> 50) & CNT_SAT);
-        if ((int64_t)nf + nrv > a.rule.hmax) {
-            rec.status = ST_OVER;
-        } else if (key == canon) {
+        if (key == canon) {
             rec.off_f = off; rec.nf = nf; rec.off_r = off + nf; rec.nr = nrv;
         } else {   // the seed is the reverse complement of the stored key
             rec.off_f = off + nf; rec.nf = nrv; rec.off_r = off; rec.nr = nf;
@@ -419,7 +436,7 @@ __global__ __launch_bounds__(256) void k_probe(ProbeArgs a) {
     }
     const uint32_t knext = (uint32_t)__shfl_down((int)rkey, 1, 64);
     if (valid && (lane == 63 || knext != rkey)) {
-        if (len == (uint32_t)NS) a.hits[r] = cnt;
+        if (len == (uint32_t)NI) a.hits[r] = cnt;
         else atomicAdd(&a.hits[r], cnt);
     }
 }
@@ -440,9 +457,10 @@ struct GatherArgs {
     uint64_t *hk;      // per hit: ((p << 1 | strand) << 5) | seed slot, or HIT_NONE
 };
 
-// Algorithm 1's vote loop. A wave takes 64 / NS whole reads at a time, lane k holding
-// seed slot k of them (the reads' hit regions are then one contiguous range of the hit
-// array). A wave prefix sum of the slots' hit counts places every slot's hits, slot
+// Algorithm 1's vote loop. A wave takes 64 / NI whole reads at a time (NI = NS * ST probe
+// records a read), lane k holding record k of them (the reads' hit regions are then one
+// contiguous range of the hit array); a hit carries its seed slot, k / ST, so that the
+// seeds of one slot of a strided index vote once for a location between them. A wave prefix sum of the slots' hit counts places every slot's hits, slot
 // by slot and forward before reverse within a slot; then the lanes take 64 hits of the
 // range at a time (coalesced position reads and hit writes), each finding its slot by
 // a binary search over the slots' starts in LDS. A forward hit q of the seed at offset
@@ -453,22 +471,22 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     __shared__ uint32_t s_nf[4][64];
     __shared__ uint64_t s_offf[4][64], s_offr[4][64];
     __shared__ int32_t s_ofs[4][64], s_len[4][64];
-    const int NS = a.ps.NS;
+    const int NI = a.ps.NS * a.ps.ST, ST = a.ps.ST;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int rpw = 64 / NS;                       // reads per wave step
-    const int nitems = rpw * NS;
+    const int rpw = 64 / NI;                       // reads per wave step
+    const int nitems = rpw * NI;
     for (int64_t r0 = wave * rpw; r0 < a.ps.nr; r0 += nwaves * rpw) {
         const int nrd = (int)min((int64_t)rpw, a.ps.nr - r0);
-        const int rl = lane / NS, i = lane - rl * NS;
-        const bool mine = lane < nrd * NS;
+        const int rl = lane / NI, i = lane - rl * NI;
+        const bool mine = lane < nrd * NI;
         const int64_t r = r0 + rl;
         uint32_t cnt = 0, nf = 0;
         uint64_t offf = 0, offr = 0;
         int o = 0, L = 0;
         if (mine) {
-            const ProbeRec p = a.pr[r * NS + i];
+            const ProbeRec p = a.pr[r * NI + i];
             L = a.len[gid(a.ps, r)];
             if (p.status == ST_OK) {
                 cnt = p.nf + p.nr;
@@ -506,7 +524,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
                 const uint32_t k = h - s_start[wv][lo];
                 const uint32_t snf = s_nf[wv][lo];
                 const int64_t so = s_ofs[wv][lo], sl = s_len[wv][lo];
-                const uint64_t slot = (uint64_t)(lo % NS);
+                const uint64_t slot = (uint64_t)((lo % NI) / ST);
                 uint64_t hv;
                 if (k < snf) {
                     const int64_t pp = (int64_t)a.positions[s_offf[wv][lo] + k] - so;
@@ -582,7 +600,9 @@ __global__ __launch_bounds__(256) void k_dedupe_light(DedupeArgs a) {
         const uint64_t prev = shfl_up64(loc, 1);
         const bool first = valid && (lane == 0 || prev != loc);
         uint32_t acc = valid ? (1u << (v & 31)) : 0u;
-        for (int d = 1; d < 32; d <<= 1) {
+        // a location's run spans up to 32 lanes (one hit per seed slot), 64 with the two
+        // seeds a slot of a stride-2 index has
+        for (int d = 1; d < 64; d <<= 1) {
             const uint32_t nb = __shfl_down(acc, d, 64);
             const uint64_t nloc = shfl_down64(loc, d);
             if (lane + d < 64 && nloc == loc) acc |= nb;
@@ -1452,6 +1472,13 @@ __device__ inline void wave_record(const ReplayArgs &a, int64_t base, int64_t k,
 
 // EditDistance(Read, Reference[p_k], lim) from what is known about location k: its
 // capped distance dc = min(D, vl + 1) for the limit vl it was verified with.
+// Seed slots that count as non-overlapping seeds of Algorithm 1 (t): the round-0 slots,
+// at offsets that are multiples of s, i.e. the first L / s slots; with a strided index
+// only those whose ST seeds all fit in the read, the first (L - ST + 1) / s of them.
+__device__ inline int round0_slots(int L, int s, int ST) {
+    return L >= ST - 1 ? (L - ST + 1) / s : 0;
+}
+
 // Returns the distance, -1 for the special value, or -2 when it is not known yet.
 __device__ inline int ed_answer(int dc, int vl, int lim) {
     if (dc <= vl) return dc <= lim ? dc : -1;
@@ -1463,11 +1490,13 @@ __device__ inline int ed_answer(int dc, int vl, int lim) {
 // that does not decide it (the location was verified with a limit below the one
 // Algorithm 1 asks for), the read records a verification request and is replayed
 // once it is answered. In the main loop a read asks for that one location at
-// exactly that limit (a short read, in the lane tile, does so for its first
-// exact_rounds rounds and then asks for every location it has not decided at the
-// full limit); in the phase that scores every remaining location it asks for
-// every remaining undecided location at the current limit, which only shrinks as
-// results come in (up to rare steps of one, answered by a further round). A read
+// exactly that limit; a short read, in the lane tile, does so only while that limit
+// is the full one, d_max + c - 1, and for at most exact_rounds rounds, and otherwise
+// asks for every unscored location it has not decided at the current limit. In the
+// phase that scores every remaining location it asks for every remaining undecided
+// location at the current limit. The limit only shrinks as results come in (up to
+// rare steps of one, answered by a further round), so a location verified at the
+// current limit is decided for every later call. A read
 // that needs a seed this pass did not probe is left to the next pass. The phase
 // that scores every remaining location only changes state at calls that return a
 // distance, so it scans for the next such location in selection order (vote count
@@ -1495,13 +1524,13 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         const bool lane_class = L <= a.lane_lmax && Kfull <= LANE_KMAX;
         const bool all_undecided = lane_class && a.round >= a.exact_rounds;
         ReadState st{DINF, DINF, -1, -1, -1};
-        const int round0 = L / a.rule.s;
+        const int round0 = round0_slots(L, a.rule.s, a.ps.ST);
         int t = 0, call = -1;
         bool looked = false, all_over = true, ended = false, unresolved = false;
         int64_t need_k = -1;
         uint32_t prefix = 0;
         // seed slot `lane`'s status, loaded once (the loops over seeds read it by lane)
-        const int stat = lane < NS ? (int)a.pr[r * NS + lane].status : ST_NONE;
+        const int stat = lane < NS ? (int)a.pr[(r * NS + lane) * a.ps.ST].status : ST_NONE;
         if constexpr (LIGHT) {
             // ---- registers: location `lane`
             const bool have = lane < C;
@@ -1541,8 +1570,8 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                     if (res == -2) {
                         unresolved = true;
                         need_k = kb;
-                        if (all_undecided)
-                            light_request(a, base, r, have && dc > vl && vl < Kfull, Kfull, false, lane);
+                        if (lane_class && (all_undecided || lim < Kfull))
+                            light_request(a, base, r, have && !scored && dc > vl && vl < lim, lim, false, lane);
                         else
                             light_request(a, base, r, lane == kb, lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
                         break;
@@ -1568,7 +1597,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                                 unresolved = true;
                                 need_k = j;
                                 // every remaining location still undecided at the limit
-                                const int lr = all_undecided ? Kfull : lim;
+                                const int lr = lim;
                                 light_request(a, base, r, have && !scored && (mask & prefix) && dc > vl && vl < lr,
                                               lane_class ? lr : (REQ_WAVE | lr), !lane_class, lane);
                                 break;
@@ -1646,11 +1675,11 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                 if (res == -2) {
                     unresolved = true;
                     need_k = kb;
-                    if (all_undecided) {
+                    if (lane_class && (all_undecided || lim < Kfull)) {
                         heavy_request(a, base, C, r, [&](int64_t k) {
                             const int dck = dc_at(k), vlk = vl_at(k);
-                            return dck > vlk && vlk < Kfull;
-                        }, Kfull, false, lane);
+                            return !scored_at(k) && dck > vlk && vlk < lim;
+                        }, lim, false, lane);
                     } else {
                         heavy_request(a, base, C, r, [&](int64_t k) { return k == kb; },
                                       lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
@@ -1699,7 +1728,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                                 unresolved = true;
                                 need_k = c0 + j;
                                 // every remaining location still undecided at the limit
-                                const int lr = all_undecided ? Kfull : lim;
+                                const int lr = lim;
                                 heavy_request(a, base, C, r, [&](int64_t k2) {
                                     const int dck = dc_at(k2), vlk = vl_at(k2);
                                     return !scored_at(k2) && (mask_at(k2) & prefix) && dck > vlk && vlk < lr;
@@ -1810,7 +1839,7 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                 if (j == rk) BM[j] = nv;
             state_update(st, rk, (int)(nv >> 32), (int64_t)(nv & 0xFFFFFFFFull), (int)((sbits >> k) & 1u));
         };
-        const int round0 = L / a.rule.s;
+        const int round0 = round0_slots(L, a.rule.s, a.ps.ST);
         int t = 0, call = -1, need_k = -1;
         int req_kind = 0, req_lim = 0;   // 0: location need_k at req_lim; 1: undecided at Kfull; 2: remaining at req_lim
         bool looked = false, all_over = true, ended = false, unresolved = false;
@@ -1818,7 +1847,7 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
         // the seed slots' statuses (2 bits each), loaded together up front
         uint64_t stw = 0;
 #pragma unroll 4
-        for (int i = 0; i < NS; i++) stw |= (uint64_t)a.pr[r * NS + i].status << (2 * i);
+        for (int i = 0; i < NS; i++) stw |= (uint64_t)a.pr[(r * NS + i) * a.ps.ST].status << (2 * i);
         for (int i = 0; i < NS; i++) {
             const int status = (int)((stw >> (2 * i)) & 3u);
             if (status == ST_NONE) { ended = true; break; }
@@ -1842,7 +1871,7 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                 if (res == -2) {
                     unresolved = true;
                     need_k = kb;
-                    req_kind = all_undecided ? 1 : 0;
+                    req_kind = (lane_class && (all_undecided || lim < Kfull)) ? 1 : 0;
                     req_lim = lim;
                     break;
                 }
@@ -1866,7 +1895,7 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                                 unresolved = true;
                                 need_k = k;
                                 req_kind = 2;
-                                req_lim = all_undecided ? Kfull : lim;
+                                req_lim = lim;
                             } else if (res >= 0) {
                                 record(k, res);
                             }
@@ -1883,15 +1912,15 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
         if (unresolved) {
             if (need_k >= 0) {
                 // the locations asked for (see k_replay), listed at the read's first slot
-                const int code = req_kind == 1 ? Kfull : (lane_class ? req_lim : (REQ_WAVE | req_lim));
-                const int lr = req_kind == 1 ? Kfull : req_lim;
+                const int code = lane_class ? req_lim : (REQ_WAVE | req_lim);
+                const int lr = req_lim;
                 uint32_t n = 0;
 #pragma unroll
                 for (int k = 0; k < TINY_LOCS; k++) {
                     const int dc = (int)(DV[k] & 0xFFFFu), vl = (int)(int16_t)(DV[k] >> 16);
                     bool want;
                     if (req_kind == 0) want = k == need_k;
-                    else if (req_kind == 1) want = dc > vl && vl < lr;
+                    else if (req_kind == 1) want = !((scored >> k) & 1u) && dc > vl && vl < lr;
                     else want = !((scored >> k) & 1u) && (M[k] & prefix) && dc > vl && vl < lr;
                     if (k < C && want) {
                         a.rq[base + k] = (int16_t)code;
@@ -2202,10 +2231,10 @@ namespace {
 
 // The workspace a batch is sized for: one chunk of up to CHUNK_READS reads with 24 hit
 // slots a read (a chunk shrinks to fit a smaller workspace; outputs do not change).
-size_t workspace_bytes_for(const Rule &rule, int64_t n_reads, int64_t total_bases, int32_t max_len) {
+size_t workspace_bytes_for(const Rule &rule, int ST, int64_t n_reads, int64_t total_bases, int32_t max_len) {
     const int NS = seeds_for_length(rule, max_len);
     const int64_t R = std::max<int64_t>(1, std::min<int64_t>(n_reads, CHUNK_READS));
-    return make_layout(n_reads, total_bases, NS, rule.hmax, R, R * 24).total;
+    return make_layout(n_reads, total_bases, NS * ST, rule.hmax, R, R * 24).total;
 }
 
 }  // namespace
@@ -2215,7 +2244,7 @@ extern "C" size_t snap_align_workspace_bytes(const snap_index *ix, int64_t n_rea
     if (!ix || n_reads < 0 || total_bases < 0 || max_len < 0 || max_len > VERIFY_LMAX || d_max < 0 ||
         !valid_params(p))
         return 0;
-    return workspace_bytes_for(make_rule(ix, d_max, p), n_reads, total_bases, max_len);
+    return workspace_bytes_for(make_rule(ix, d_max, p), std::max(1, ix->d.stride), n_reads, total_bases, max_len);
 }
 
 namespace {
@@ -2275,25 +2304,26 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     if (maxlen_u & 0x80000000u) return SNAP_EINVAL;
     const int maxL = (int)maxlen_u;
     const int NS = std::max(1, seeds_for_length(rule, maxL));
+    const int ST = std::max(1, ix->d.stride);   // probe records per seed slot
     const int Kmax = dmax_for_length(rule, maxL) + rule.c - 1;
-    if (Kmax > VERIFY_KMAX || maxL > VERIFY_LMAX) return SNAP_EINVAL;
+    if (Kmax > VERIFY_KMAX || maxL > VERIFY_LMAX || NS * ST > 64) return SNAP_EINVAL;
     // the fixed scratch takes exactly the batches snap_align_workspace_bytes sizes within it
-    if (fixed_scratch && workspace_bytes_for(rule, n_reads, B, maxL) > ws_bytes) return SNAP_ETOOBIG;
+    if (fixed_scratch && workspace_bytes_for(rule, ST, n_reads, B, maxL) > ws_bytes) return SNAP_ETOOBIG;
 
     // chunk size and pool from the workspace
     int64_t R = std::min<int64_t>(n_reads, tune.chunk_reads > 0 ? tune.chunk_reads : CHUNK_READS);
-    Layout l = make_layout(n_reads, B, NS, rule.hmax, R, 0);
+    Layout l = make_layout(n_reads, B, NS * ST, rule.hmax, R, 0);
     while (l.total > ws_bytes && R > 1) {
         R = std::max<int64_t>(1, R / 2);
-        l = make_layout(n_reads, B, NS, rule.hmax, R, 0);
+        l = make_layout(n_reads, B, NS * ST, rule.hmax, R, 0);
     }
     if (l.total > ws_bytes) return SNAP_ENOMEM;
     {
         int64_t extra = (int64_t)((ws_bytes - l.total) / POOL_SLOT_BYTES);
-        l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots + extra);
+        l = make_layout(n_reads, B, NS * ST, rule.hmax, R, l.pool_slots + extra);
         while (l.total > ws_bytes) {
             const int64_t over = (int64_t)((l.total - ws_bytes) / POOL_SLOT_BYTES) + 64;
-            l = make_layout(n_reads, B, NS, rule.hmax, R, l.pool_slots - over);
+            l = make_layout(n_reads, B, NS * ST, rule.hmax, R, l.pool_slots - over);
         }
     }
     // two workers (a host thread and a stream each, and a chunk part of the workspace
@@ -2306,13 +2336,13 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     const int max_workers = fixed_scratch ? 1 : std::min<int64_t>(tune.workers > 0 ? tune.workers : 2,
                                                                   (n_reads + R - 1) / R);
     for (int w = std::min(max_workers, MAX_WORKERS); w >= 2; w--) {
-        Layout lw = make_layout(n_reads, B, NS, rule.hmax, R, 0, w);
+        Layout lw = make_layout(n_reads, B, NS * ST, rule.hmax, R, 0, w);
         if (lw.total > ws_bytes) continue;
         const int64_t extra = (int64_t)((ws_bytes - lw.total) / ((size_t)w * POOL_SLOT_BYTES));
-        lw = make_layout(n_reads, B, NS, rule.hmax, R, lw.pool_slots + extra, w);
+        lw = make_layout(n_reads, B, NS * ST, rule.hmax, R, lw.pool_slots + extra, w);
         while (lw.total > ws_bytes) {
             const int64_t over = (int64_t)((lw.total - ws_bytes) / ((size_t)w * POOL_SLOT_BYTES)) + 64;
-            lw = make_layout(n_reads, B, NS, rule.hmax, R, lw.pool_slots - over, w);
+            lw = make_layout(n_reads, B, NS * ST, rule.hmax, R, lw.pool_slots - over, w);
         }
         if (lw.pool_slots >= 16 * R) {
             l = lw;
@@ -2479,9 +2509,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
           const int64_t b0 = std::min<int64_t>(a0 + R, list_len);
           for (int64_t r0 = a0; r0 < b0;) {
             int64_t nr = std::min<int64_t>(R, b0 - r0);
-            Pass ps{ridx, r0, nr, NSp, Kcap, final_pass};
+            Pass ps{ridx, r0, nr, NSp, Kcap, final_pass, ST};
             ProbeArgs pa{ix->d, rcode, rmask, roff, lengths, ps, rule, sh, probe, hits};
-            const int64_t pthreads = nr * NSp;   // one lane per (read, seed slot)
+            const int64_t pthreads = nr * NSp * ST;   // one lane per (read, seed slot, seed of the slot)
             hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, hits, nr, 0u);
             timed("probe", st, [&] { hipLaunchKernelGGL(k_probe, dim3((unsigned)((pthreads + 255) / 256)), dim3(256), 0, st, pa); });
             size_t tb = scan_tmp_bytes(nr + 1);
@@ -2515,7 +2545,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             }
             if (total > 0) {
                 GatherArgs ga{probe, ix->d.positions, ix->d.G, ix->d.s, lengths, ps, hoff, hk};
-                const int64_t rpb = 4 * (64 / NSp);   // reads per block step (4 waves)
+                const int64_t rpb = 4 * (64 / (NSp * ST));   // reads per block step (4 waves)
                 const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + rpb - 1) / rpb, 8192));
                 timed("gather", st, [&] { hipLaunchKernelGGL(k_gather, dim3(gb), dim3(256), 0, st, ga); });
             }

@@ -408,6 +408,7 @@ extern "C" int snap_index_build_progress(const uint8_t *genome, uint64_t len, in
     ix->d.nbuckets = h.nbuckets;
     ix->d.log2_buckets = h.log2b;
     ix->d.s = seed_len;
+    ix->d.stride = 1;
     ix->windows = h.windows;
     ix->distinct_keys = h.distinct;
     ix->position_entries = h.positions.size();
@@ -421,6 +422,7 @@ extern "C" int snap_index_info(const snap_index *ix, snap_index_sizes *info) {
     std::memset(info, 0, sizeof(*info));
     info->genome_len = ix->d.G;
     info->seed_len = ix->d.s;
+    info->stride = ix->d.stride;
     info->windows = ix->windows;
     info->distinct_keys = ix->distinct_keys;
     info->table_slots = ix->d.nbuckets * SLOTS_PER_BUCKET;

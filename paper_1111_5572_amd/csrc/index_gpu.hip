@@ -105,10 +105,12 @@ __device__ inline bool window_has_n(const uint32_t *gmask, uint64_t q, int s) {
 }
 
 // The records window q gives: bit 0 forward (its code is canonical), bit 1 reverse
-// (its reverse complement is), none if it holds an N or lies past the last window.
+// (its reverse complement is), none if it holds an N, lies past the last window or is
+// not at a multiple of the index's stride (Section 3.1's footnote: a window slid
+// `stride` bases at a time; stride 1 indexes every overlapping window).
 __device__ inline uint32_t window_records(const uint32_t *gcode, const uint32_t *gmask, uint64_t q, uint64_t nwin,
-                                          int s, uint64_t &canon) {
-    if (q >= nwin || window_has_n(gmask, q, s)) return 0;
+                                          int s, uint32_t stride, uint64_t &canon) {
+    if (q >= nwin || (stride > 1 && q % stride != 0) || window_has_n(gmask, q, s)) return 0;
     const uint64_t fw = window_code(gcode, q, s), rc = rc_code(fw, s);
     canon = fw < rc ? fw : rc;
     return (fw == canon ? 1u : 0u) | (rc == canon ? 2u : 0u);
@@ -124,11 +126,12 @@ __device__ inline uint64_t emit_window(int k) {
 // Pass 1: per block, the records its windows give (low 32 bits) and its N-free windows
 // (high 32 bits).
 __global__ __launch_bounds__(EMIT_THREADS) void k_count_records(const uint32_t *gcode, const uint32_t *gmask,
-                                                                uint64_t nwin, int s, uint64_t *block_counts) {
+                                                                uint64_t nwin, int s, uint32_t stride,
+                                                                uint64_t *block_counts) {
     uint32_t recs = 0, free_w = 0;
     for (int k = 0; k < EMIT_WPT; k++) {
         uint64_t canon = 0;
-        const uint32_t f = window_records(gcode, gmask, emit_window(k), nwin, s, canon);
+        const uint32_t f = window_records(gcode, gmask, emit_window(k), nwin, s, stride, canon);
         recs += (f & 1) + (f >> 1);
         free_w += f ? 1 : 0;
     }
@@ -150,13 +153,14 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_count_records(const uint32_t *
 // of the block counts) in window order: waves in order, and within a wave 64 windows at
 // a time, each lane's records placed after those of the lanes before it (ballots).
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit_records(const uint32_t *gcode, const uint32_t *gmask,
-                                                               uint64_t nwin, int s, const uint64_t *block_off,
-                                                               uint64_t *keys, uint32_t *vals) {
+                                                               uint64_t nwin, int s, uint32_t stride,
+                                                               const uint64_t *block_off, uint64_t *keys,
+                                                               uint32_t *vals) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t recs = 0;
     for (int k = 0; k < EMIT_WPT; k++) {
         uint64_t canon = 0;
-        const uint32_t f = window_records(gcode, gmask, emit_window(k), nwin, s, canon);
+        const uint32_t f = window_records(gcode, gmask, emit_window(k), nwin, s, stride, canon);
         recs += (f & 1) + (f >> 1);
     }
     for (int o = 32; o > 0; o >>= 1) recs += (uint32_t)__shfl_xor((int)recs, o, 64);
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit_records(const uint32_t *g
     for (int k = 0; k < EMIT_WPT; k++) {
         const uint64_t q = emit_window(k);
         uint64_t canon = 0;
-        const uint32_t f = window_records(gcode, gmask, q, nwin, s, canon);
+        const uint32_t f = window_records(gcode, gmask, q, nwin, s, stride, canon);
         const uint64_t b0 = __ballot(f & 1), b1 = __ballot(f & 2);
         uint64_t my = at + __popcll(b0 & below) + __popcll(b1 & below);
         if (f & 1) { keys[my] = canon << 1; vals[my] = (uint32_t)q; my++; }
@@ -264,7 +268,8 @@ struct DevProgress {
     }
 };
 
-int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, const DevProgress &prog, snap_index *ix) {
+int build_device(const uint8_t *genome, uint64_t G, int s, uint32_t stride, hipStream_t st, const DevProgress &prog,
+                 snap_index *ix) {
     const uint64_t ncw = (G + 15) / 16 + GENOME_PAD_WORDS, nmw = (G + 31) / 32 + GENOME_PAD_WORDS;
     const int64_t nblk = (int64_t)((G + 31) / 32);
     DevBuf dg, gcode, gmask;
@@ -289,7 +294,7 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, const
     RC_OK(bcnt.alloc(nb * 8));
     RC_OK(boff.alloc(nb * 8));
     RC_OK(total.alloc(16));
-    hipLaunchKernelGGL(k_count_records, dim3((unsigned)nb), dim3(EMIT_THREADS), 0, st, gc, gm, nwin, s,
+    hipLaunchKernelGGL(k_count_records, dim3((unsigned)nb), dim3(EMIT_THREADS), 0, st, gc, gm, nwin, s, stride,
                        (uint64_t *)bcnt.p);
     DEV_OK(hipGetLastError());
     uint64_t sums[2] = {0, 0};   // records, N-free windows
@@ -323,7 +328,7 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, const
     RC_OK(k1.alloc(nrec * 8));
     RC_OK(v0.alloc(nrec * 4));
     RC_OK(v1.alloc(nrec * 4));
-    hipLaunchKernelGGL(k_emit_records, dim3((unsigned)nb), dim3(EMIT_THREADS), 0, st, gc, gm, nwin, s,
+    hipLaunchKernelGGL(k_emit_records, dim3((unsigned)nb), dim3(EMIT_THREADS), 0, st, gc, gm, nwin, s, stride,
                        (const uint64_t *)boff.p, (uint64_t *)k0.p, (uint32_t *)v0.p);
     DEV_OK(hipGetLastError());
     DEV_OK(hipStreamSynchronize(st));
@@ -378,6 +383,7 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, const
 
     ix->d.G = G;
     ix->d.s = s;
+    ix->d.stride = (int32_t)stride;
     ix->d.nbuckets = nbuckets;
     ix->d.log2_buckets = log2b;
     ix->windows = sums[1];
@@ -397,16 +403,18 @@ int build_device(const uint8_t *genome, uint64_t G, int s, hipStream_t st, const
 
 }  // namespace
 
-extern "C" int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_len, void *stream,
-                                       snap_progress_fn progress, void *ctx, snap_index **out) {
+extern "C" int snap_index_build_strided(const uint8_t *genome, uint64_t len, int32_t seed_len, int32_t stride,
+                                        void *stream, snap_progress_fn progress, void *ctx, snap_index **out) {
     if (!out) return SNAP_EINVAL;
     *out = nullptr;
     if (!genome || seed_len < 1 || seed_len > 31 || len < (uint64_t)seed_len || len >= (1ull << 32))
         return SNAP_EINVAL;
+    if (stride != 1 && stride != 2 && stride != 4) return SNAP_EINVAL;
     snap_index *ix = new (std::nothrow) snap_index();
     if (!ix) return SNAP_ENOMEM;
     if (hipGetDevice(&ix->device) != hipSuccess) { delete ix; return SNAP_EDEVICE; }
-    const int rc = build_device(genome, len, seed_len, (hipStream_t)stream, DevProgress{progress, ctx}, ix);
+    const int rc = build_device(genome, len, seed_len, (uint32_t)stride, (hipStream_t)stream,
+                                DevProgress{progress, ctx}, ix);
     if (rc != SNAP_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         snap_index_free(ix);
@@ -414,6 +422,11 @@ extern "C" int snap_index_build_device(const uint8_t *genome, uint64_t len, int3
     }
     *out = ix;
     return SNAP_OK;
+}
+
+extern "C" int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_len, void *stream,
+                                       snap_progress_fn progress, void *ctx, snap_index **out) {
+    return snap_index_build_strided(genome, len, seed_len, 1, stream, progress, ctx, out);
 }
 
 extern "C" int snap_debug_index_download(const snap_index *ix, int32_t which, void *host_dst, uint64_t bytes) {

@@ -36,6 +36,7 @@ struct DevIndex {
     uint64_t nbuckets;
     int32_t log2_buckets;
     int32_t s;
+    int32_t stride;              // windows at positions q with q % stride == 0 are indexed
 };
 
 // 64-bit finalizer (MurmurHash3 fmix64, Appleby): spreads a seed code over the table.

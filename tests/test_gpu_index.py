@@ -3,8 +3,6 @@
 table entries (an entry's slot depends on the order of the concurrent insertions, so
 entries are compared sorted by key), and identical alignments through either index,
 which are also the oracle's. Integer work: tolerance zero."""
-import os
-
 import numpy as np
 import pytest
 
@@ -134,20 +132,62 @@ def _table_digest(tab):
     return int(acc)
 
 
-@pytest.mark.skipif(not os.environ.get("SNAP_LARGE_TESTS"), reason="1.1 Gbase genome (about 80 GB of host "
-                    "memory, minutes); set SNAP_LARGE_TESTS=1")
-def test_device_index_over_2e30_records(snapgpu, synth_mod):
-    """More records than one batch of the device radix sort (2^30): positions identical
-    to the host build's, table entries identical by an order-free digest."""
+def test_device_index_over_2e30_records(snapgpu, oracle_mod, synth_mod):
+    """More records than 2^30 (1.1 Gbase uniform genome, one record per window): every
+    window position appears in the positions array (once, twice for a palindrome), and
+    reads aligned through this index equal the oracle's on all five outputs (the oracle's
+    index is built from the same genome; the host build is not needed)."""
+    from synth.workloads import TINY
     g = synth_mod.genome_uniform(1_100_000_000, 9)
-    h = snapgpu.Index(g, 20)
+    say(f"[over 2^30 records] G={len(g)}")
     d = snapgpu.Index(g, 20, on_device=True)
     try:
-        sh, sd = h.sizes(), d.sizes()
-        assert sh == sd and sh["position_entries"] > (1 << 30), (sh, sd)
-        for w in ("gcode", "gmask", "positions"):
-            assert np.array_equal(h.download(w), d.download(w)), w
-        assert _table_digest(h.download("table")) == _table_digest(d.download("table"))
+        sz = d.sizes()
+        nwin = len(g) - 20 + 1
+        assert sz["position_entries"] > (1 << 30) and sz["windows"] == nwin, sz
+        pos = d.download("positions")
+        pos.sort()
+        first = np.ones(pos.shape[0], dtype=bool)
+        first[1:] = pos[1:] != pos[:-1]
+        uniq = pos[first]
+        del pos
+        assert uniq.shape[0] == nwin and int(uniq[0]) == 0 and int(uniq[-1]) == nwin - 1
+        assert sz["position_entries"] - nwin < 10_000   # palindromic 20-mers: about G / 4^10
+        del uniq, first
+        w = TINY.scaled(n_reads=4_000)
+        reads = w.make_reads(g)
+        out = gpu_align(snapgpu, d, reads, w.params.d_max, snapgpu.params_from(w.params))
     finally:
-        h.close()
         d.close()
+    oix = oracle_mod.Index(g, 20, threads=16)
+    nbad, rep = compare(out, oracle_align(oracle_mod, oix, reads, w.params), reads, "over 2^30 records")
+    oix.close()
+    assert nbad == 0, rep
+
+
+def test_alignments_beyond_2e31(snapgpu, oracle_mod, synth_mod):
+    """Locations at genome positions past 2^31: the genome is an N run of 2^31 + 4,321
+    bases followed by 3 Mbase of the repeat recipe (segmental duplicates, tandem arrays);
+    reads from the tail (both strands, substitutions and indels, 100 and 250 bp) align
+    bit-exact with the oracle on all five outputs."""
+    from synth.workloads import HUMAN
+    pad = (1 << 31) + 4_321
+    w = HUMAN.scaled(genome_len=3_000_000, n_reads=8_000)
+    tail = w.make_genome()
+    reads = w.make_reads(tail)
+    g = np.empty(pad + tail.shape[0], dtype=np.uint8)
+    g[:pad] = ord("N")
+    g[pad:] = tail
+    del tail
+    say(f"[beyond 2^31] G={len(g)} reads={reads.n}")
+    d = snapgpu.Index(g, 20, on_device=True)
+    try:
+        out = gpu_align(snapgpu, d, reads, w.params.d_max, snapgpu.params_from(w.params))
+    finally:
+        d.close()
+    hit = out[0] >= 0
+    assert hit.mean() > 0.9 and int(out[0][hit].min()) >= pad
+    oix = oracle_mod.Index(g, 20, threads=16)
+    nbad, rep = compare(out, oracle_align(oracle_mod, oix, reads, w.params), reads, "beyond 2^31")
+    oix.close()
+    assert nbad == 0, rep
