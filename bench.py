@@ -42,15 +42,17 @@ def log(*a):
 
 
 INDEX_ON_HOST = False   # --host-index
+INDEX_STRIDE = 1        # --stride
 
 
 def build_index(g, seed_len):
     """Device index of the genome, built by the library's device kernels (or, with
-    --host-index, on the host, logging each finished stage: minutes for a large genome)."""
+    --host-index, on the host, logging each finished stage: minutes for a large genome;
+    with --stride, the strided index of Section 3.1's footnote)."""
     import paper_1111_5572_amd as snapgpu
     t0 = time.time()
     report = lambda stage: log(f"  index: {stage} ({time.time() - t0:.3f}s)")
-    return snapgpu.Index(g, seed_len, progress=report, on_device=not INDEX_ON_HOST)
+    return snapgpu.Index(g, seed_len, progress=report, on_device=not INDEX_ON_HOST, stride=INDEX_STRIDE)
 
 
 HMAX_SWEEP = (10, 25, 50, 100, 200, 300, 500, 1000, 2000)
@@ -266,7 +268,7 @@ def oracle_check(g, reads, w, got, seconds, single_seconds=4.0):
     import oracle
     threads = oracle_threads()
     t = time.time()
-    oix = oracle.Index(g, w.params.seed_len, threads=threads)
+    oix = oracle.Index(g, w.params.seed_len, threads=threads, stride=INDEX_STRIDE)
     log(f"oracle index in {time.time() - t:.1f}s ({threads} threads)")
     op = oracle.params_from(w.params)
     rng = np.random.default_rng(7)
@@ -764,7 +766,7 @@ def bench_plain(args, w, dev):
                                 else sorted({int(x) for x in np.unique(reads.lengths)[:4]})),
                    "seed_len": w.params.seed_len,
                    "seeds_per_read": w.params.n_min, "d_max": w.params.d_max, "conf_c": w.params.conf_c,
-                   "max_hits": w.params.max_hits},
+                   "max_hits": w.params.max_hits, "index_stride": INDEX_STRIDE},
         "gbases_per_s": round(gbases_per_s, 4),
         "timed_region": "reads and index resident in HBM; no profiling in the timed steps",
         "with_host_copies": streamed,
@@ -799,6 +801,8 @@ def main():
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule")
     ap.add_argument("--host-index", action="store_true", help="build the index on the host (snap_index_build)")
+    ap.add_argument("--stride", type=int, default=1,
+                    help="index only the windows at multiples of this stride (1, 2 or 4; device build)")
     ap.add_argument("--accuracy", action="store_true",
                     help="h_max sweep: aligned / error rates and reads/s for 125 bp reads at 2%% errors")
     ap.add_argument("--index-only", action="store_true",
@@ -813,8 +817,12 @@ def main():
                     help="only run the library's plain copy kernel over this many bytes, 3 times "
                          "(the known-size reference for HBM byte counters)")
     args = ap.parse_args()
-    global INDEX_ON_HOST
+    global INDEX_ON_HOST, INDEX_STRIDE
     INDEX_ON_HOST = args.host_index
+    INDEX_STRIDE = args.stride
+    if INDEX_STRIDE != 1 and INDEX_ON_HOST:
+        print(json.dumps({"error": "a strided index is built on the device only"}), flush=True)
+        sys.exit(2)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

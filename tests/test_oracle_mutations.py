@@ -1,0 +1,63 @@
+"""The oracle's pins catch plausible mistakes in Algorithm 1: each one-line change below
+(a wrong limit case, a boundary test off by one, a dropped orientation, a wrong tie-break,
+a shorter text window, an early return where the paper has none) is applied to a copy of
+oracle.c, and the copy must fail at least one of the oracle's CPU pin tests."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (what the change breaks, original line, mutated line)
+MUTATIONS = [
+    ("d_limit, third case: d_best - 1 (Algorithm 1)",
+     "return st->d_best - 1;", "return st->d_best;"),
+    ("d_limit, third case taken as the second",
+     "return st->d_best - 1;", "return st->d_best + c - 1;"),
+    ("early multiple-hits return needs d_best < c",
+     "if (st.d_best < c && st.d_second < st.d_best + c) {", "if (st.d_best <= c && st.d_second < st.d_best + c) {"),
+    ("single call needs d_second >= d_best + c",
+     "if (st.d_best <= dmax && st.d_second >= st.d_best + c) call = 1;",
+     "if (st.d_best <= dmax && st.d_second > st.d_best + c) call = 1;"),
+    ("h_max counts both orientations",
+     "entries += (fhi - flo) + (rhi - rlo);", "entries += (fhi - flo);"),
+    ("t counts only round-0 seeds",
+     "if (o % s == 0 && np == stride) t++;", "t++;"),
+    ("t does not count seeds over h_max",
+     "if (entries > hmax) { stt->seeds_over_limit++; continue; }",
+     "if (entries > hmax) { stt->seeds_over_limit++; if (o % s == 0) t++; continue; }"),
+    ("selection ties go to the smaller p",
+     "if (k < 0 || w->c[i].hits > w->c[k].hits) k = i;", "if (k < 0 || w->c[i].hits >= w->c[k].hits) k = i;"),
+    ("a bucket keeps the lower p on equal distance",
+     "} else if (d < w->b[j].d || (d == w->b[j].d && p < w->b[j].p)) {", "} else if (d < w->b[j].d) {"),
+    ("best-location ties: forward before reverse",
+     "if (x->d < y->d || (x->d == y->d && (x->p < y->p || (x->p == y->p && x->strand < y->strand)))) bi = j;",
+     "if (x->d < y->d || (x->d == y->d && (x->p < y->p || (x->p == y->p && x->strand > y->strand)))) bi = j;"),
+    ("text window of L + limit bases",
+     "int64_t want = (int64_t)L + (lim > 0 ? lim : 0);", "int64_t want = (int64_t)L + (lim > 0 ? lim - 1 : 0);"),
+    ("no early return while scoring the remaining locations",
+     "while ((k = select_unscored(w)) >= 0) score(ix, w, &st, k, L, dmax, pr, stt, lg);",
+     "while ((k = select_unscored(w)) >= 0) { score(ix, w, &st, k, L, dmax, pr, stt, lg); "
+     "if (st.d_best < c && st.d_second < st.d_best + c) { call = 2; break; } }"),
+]
+
+PIN_TESTS = ["tests/test_oracle_algorithm1.py", "tests/test_oracle_branches.py", "tests/test_oracle_pins.py",
+             "tests/test_oracle_invariants.py", "tests/test_oracle_strided.py"]
+
+
+@pytest.mark.parametrize("what,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_mutation_fails_a_pin(tmp_path, synth_mod, what, old, new):
+    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    assert src.count(old) == 1, f"the line to mutate is not in oracle.c once: {old}"
+    for d in ("oracle", "synth", "tests"):
+        shutil.copytree(os.path.join(ROOT, d), tmp_path / d,
+                        ignore=shutil.ignore_patterns("__pycache__", "liboracle.so", "*.tmp"))
+    (tmp_path / "oracle" / "oracle.c").write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o",
+                           str(tmp_path / "oracle" / "liboracle.so"), str(tmp_path / "oracle" / "oracle.c")])
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-m", "not gpu", "-p", "no:cacheprovider",
+                        *PIN_TESTS], cwd=tmp_path, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 1, f"mutation survived every pin: {what}\n{r.stdout[-2000:]}"
