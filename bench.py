@@ -678,6 +678,15 @@ def bench_plain(args, w, dev):
     index_s = time.time() - t
     sizes = gix.sizes()
     log(f"index built and resident in {index_s:.1f}s: {sizes}")
+    dup = None
+    if args.dup_window:
+        torch.cuda.synchronize()
+        t = time.time()
+        gix.dup_classes(args.dup_window)
+        torch.cuda.synchronize()
+        dup = {"window": args.dup_window, "build_s": round(time.time() - t, 3),
+               "device_bytes": gix.sizes()["device_bytes"] - sizes["device_bytes"]}
+        log(f"exact-duplicate classes of {args.dup_window}-base windows in {dup['build_s']}s")
 
     rb = torch.from_numpy(reads.bases).to(dev)
     ln = torch.from_numpy(reads.lengths).to(dev)
@@ -772,6 +781,7 @@ def bench_plain(args, w, dev):
         "with_host_copies": streamed,
         "index_build_s": round(index_s, 2), "index_build": "host" if INDEX_ON_HOST else "device",
         "index_device_bytes": sizes["device_bytes"],
+        "dup_classes": dup,
         "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
         "profiled_ms_per_step": round(prof_ms, 3),
         "kernel_ms_per_step": {k: round(v[1] / prof_steps, 4) for k, v in kern.items()},
@@ -801,6 +811,8 @@ def main():
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule")
     ap.add_argument("--host-index", action="store_true", help="build the index on the host (snap_index_build)")
+    ap.add_argument("--dup-window", type=int, default=0,
+                    help="attach exact-duplicate classes of windows of this many bases (0: none)")
     ap.add_argument("--stride", type=int, default=1,
                     help="index only the windows at multiples of this stride (1, 2 or 4; device build)")
     ap.add_argument("--accuracy", action="store_true",

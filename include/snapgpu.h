@@ -54,7 +54,7 @@ typedef struct {
     uint64_t position_entries;/* entries of the position array (windows + palindromic windows) */
     uint64_t device_bytes;    /* HBM held by the index */
     int32_t device;           /* HIP device ordinal the index lives on */
-    int32_t reserved2;
+    int32_t dup_window;       /* W of the attached exact-duplicate classes, 0 if none */
 } snap_index_sizes;
 
 /*
@@ -108,6 +108,22 @@ int snap_index_build_device(const uint8_t *genome, uint64_t len, int32_t seed_le
  * Errors: as snap_index_build_device, and SNAP_EINVAL for any other stride. */
 int snap_index_build_strided(const uint8_t *genome, uint64_t len, int32_t seed_len, int32_t stride, void *stream,
                              snap_progress_fn progress, void *ctx, snap_index **out);
+
+/* Exact-duplicate classes (Section 4.2, "Approach": identical substrings of a read's
+ * length found by hashing, so that each repeated string is compared once), attached to
+ * the index: for every genome position q, the smallest position whose `window`-base
+ * window is identical to q's (bases as codes, an N equal to every N), q itself when no
+ * earlier one is or when q's window runs past the genome's end. Built on the device from
+ * the index's packed genome (a rolling 64-bit hash of every window, a radix sort, and a
+ * word-by-word comparison of every window with its hash run's first one, so a hash
+ * collision never merges two classes). Afterwards snap_align verifies, for each read
+ * with L + d_max(L) + c - 1 <= window, one location per class and strand among the read's
+ * locations and answers the others from it (their text windows are identical, so every
+ * edit distance is); outputs do not change. Calling it again replaces the classes.
+ * Device memory: 4 bytes per base kept with the index; about 24 bytes per window more
+ * while building. The current device must be the index's. Errors: SNAP_EINVAL (NULL
+ * index, window < 1, another device), SNAP_ENOMEM, SNAP_EDEVICE. */
+int snap_index_dup_classes(snap_index *ix, int32_t window, void *stream);
 
 /* Release the index and its device memory. NULL is accepted. */
 int snap_index_free(snap_index *ix);
@@ -371,6 +387,7 @@ typedef struct {
     int64_t workers;      /* most chunk workers (host thread + stream) one call used */
     int64_t lv_steps_first; /* of lv_steps, those of the first verification of every location
                              * (the rest verified what replays asked for) */
+    int64_t dup_aliases;  /* locations answered by their exact-duplicate representative */
 } snap_counters;
 
 int snap_profile_counters(snap_counters *out);

@@ -46,6 +46,10 @@ int snap_debug_copy(const void *src, void *dst, uint64_t bytes, void *stream);
  * table_slots, position_entries). Synchronous. Errors: SNAP_EINVAL, SNAP_EDEVICE. */
 int snap_debug_index_download(const snap_index *ix, int32_t which, void *host_dst, uint64_t bytes);
 
+/* Copy the index's exact-duplicate class array (count = genome length entries of
+ * uint32) to host memory. SNAP_EINVAL when the index has no classes or count differs. */
+int snap_debug_dup_download(const snap_index *ix, uint32_t *host_dst, uint64_t count);
+
 #ifdef __cplusplus
 }
 #endif

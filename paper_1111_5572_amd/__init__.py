@@ -37,7 +37,7 @@ class IndexSizes(ctypes.Structure):
     _fields_ = [("genome_len", ctypes.c_uint64), ("seed_len", ctypes.c_int32), ("stride", ctypes.c_int32),
                 ("windows", ctypes.c_uint64), ("distinct_keys", ctypes.c_uint64),
                 ("table_slots", ctypes.c_uint64), ("position_entries", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32), ("dup_window", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -105,7 +105,7 @@ class ServerStats(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("passes", "reads", "seed_slots", "hits", "locations", "lv_steps", "second_pass_reads", "requests",
-                 "workers", "lv_steps_first")]
+                 "workers", "lv_steps_first", "dup_aliases")]
 
 
 def lib():
@@ -126,6 +126,10 @@ def lib():
         L.snap_index_build_device.restype = ctypes.c_int
         L.snap_index_build_strided.argtypes = [P, u64, i32, i32, P, PROGRESS_FN, P, ctypes.POINTER(P)]
         L.snap_index_build_strided.restype = ctypes.c_int
+        L.snap_index_dup_classes.argtypes = [P, i32, P]
+        L.snap_index_dup_classes.restype = ctypes.c_int
+        L.snap_debug_dup_download.argtypes = [P, P, u64]
+        L.snap_debug_dup_download.restype = ctypes.c_int
         L.snap_debug_index_download.argtypes = [P, i32, P, u64]
         L.snap_debug_index_download.restype = ctypes.c_int
         L.snap_index_free.argtypes = [P]
@@ -267,6 +271,17 @@ class Index:
         }[which]
         out = np.empty(shape, dtype=dt)
         _check(lib().snap_debug_index_download(self._h, idx, out.ctypes.data, out.nbytes), "snap_debug_index_download")
+        return out
+
+    def dup_classes(self, window: int, stream=None):
+        """Attach exact-duplicate classes of `window`-base windows (snap_index_dup_classes)."""
+        _check(lib().snap_index_dup_classes(self._h, int(window), _stream_ptr(stream)), "snap_index_dup_classes")
+
+    def download_dup_classes(self) -> np.ndarray:
+        """The class array (one uint32 per genome position)."""
+        G = self.sizes()["genome_len"]
+        out = np.empty(G, dtype=np.uint32)
+        _check(lib().snap_debug_dup_download(self._h, out.ctypes.data, G), "snap_debug_dup_download")
         return out
 
     def sizes(self) -> dict:

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("index.hip", "index_gpu.hip", "align.hip", "server.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("index.hip", "index_gpu.hip", "dups.hip", "align.hip", "server.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "snap_internal.h"), os.path.join(ROOT, "include", "snapgpu.h"),
            os.path.join(ROOT, "include", "snapgpu_debug.h")]
 LIB = os.path.join(HERE, "libsnapgpu.so")

@@ -1266,6 +1266,47 @@ __global__ __launch_bounds__(64) void k_verify_steal(StealArgs a) {
 
 // Locations hit by none of the first seed slots (`bits`): left for verification on
 // request (capped distance unknown above -1).
+// Exact-duplicate classes (Section 4.2): for a read whose text window L + d_max(L) + c - 1
+// fits the class window, location k's representative is the read's location on the same
+// strand at the first position of k's class. That location exists whenever k's class is
+// not its own: the two W-base windows are identical, so every seed that hits k hits it at
+// the same offset, with the same counts (with a strided index the other position may not
+// be indexed; then k stays its own). k itself otherwise. An alias is left unverified: its
+// representative's results answer it (the replays take them). *nalias counts aliases.
+__global__ void k_dup_alias(DevIndex ix, const uint64_t *key, const uint32_t *cread, const int64_t *coff,
+                            const int32_t *len, Pass ps, Rule rule, const int64_t *ncand_ptr, uint32_t *alias,
+                            uint16_t *dcap, int16_t *vlim, uint32_t *steps, unsigned long long *nalias) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = *ncand_ptr;
+    uint32_t al = (uint32_t)k;
+    if (k < n) {
+        const uint32_t r = cread[k];
+        const int L = len[gid(ps, r)];
+        if (L + dmax_for_length(rule, L) + rule.c - 1 <= ix.dup_w) {
+            const uint64_t kk = key[k];
+            const uint64_t p = kk >> 1;
+            const uint64_t h = ix.rep[p];
+            if (h != p) {
+                const uint64_t want = (h << 1) | (kk & 1);
+                int64_t lo = coff[r], hi = coff[r + 1];
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (key[mid] < want) lo = mid + 1; else hi = mid;
+                }
+                if (lo < coff[r + 1] && key[lo] == want) al = (uint32_t)lo;
+            }
+        }
+        alias[k] = al;
+        if (al != (uint32_t)k) {
+            dcap[k] = 0xFFFF;
+            vlim[k] = -1;
+            if (steps) steps[k] = 0;
+        }
+    }
+    const uint64_t b = __ballot(k < n && al != (uint32_t)k);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(nalias, (unsigned long long)__popcll(b));
+}
+
 __global__ void k_mark_late(const uint32_t *mask, const int64_t *ncand_ptr, uint32_t bits, uint16_t *dcap,
                             int16_t *vlim, uint32_t *steps) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1317,6 +1358,7 @@ struct ReplayArgs {
     Pass ps;
     Rule rule;
     Shifts sh;
+    const uint32_t *alias;      // per location: its exact-duplicate representative (null: no classes)
     uint8_t *rflag;             // per chunk read: RF_DONE / RF_PENDING / RF_REPLAY
     int16_t *rq;                // per location: requested verify limit (REQ_WAVE-tagged for long reads)
     uint32_t *req_area;         // per read, at its first location slot: the locations it asks for
@@ -1393,8 +1435,34 @@ __device__ inline int wave_argmax6(uint32_t v) {
 // A read's verification requests: the locations whose `want` is set (all lanes of
 // the wave call this together), each with limit `code`, listed at the read's first
 // location slot.
+//
+// With exact-duplicate classes a location and its representative (an identical text
+// window, see k_dup_alias) have the same distance, so a replay takes whichever of the two
+// was verified with the higher limit, and a location does not ask for a verification
+// when its representative asks in the same round.
+__device__ inline uint32_t load_dv(const ReplayArgs &a, int64_t i) {
+    uint32_t dc = a.dcap[i];
+    int vl = a.vlim[i];
+    if (a.alias) {
+        const int64_t j = a.alias[i];
+        if (j != i && a.vlim[j] > vl) {
+            dc = a.dcap[j];
+            vl = a.vlim[j];
+        }
+    }
+    return dc | ((uint32_t)(uint16_t)vl << 16);
+}
+__device__ inline int dv_dc(uint32_t dv) { return (int)(dv & 0xFFFFu); }
+__device__ inline int dv_vl(uint32_t dv) { return (int)(int16_t)(dv >> 16); }
+
 __device__ inline void light_request(const ReplayArgs &a, int64_t base, int64_t r, bool want, int code,
                                      bool wave_tile, int lane) {
+    if (a.alias) {
+        const int64_t cnt = a.count[r];
+        const int64_t j = lane < cnt ? (int64_t)a.alias[base + lane] - base : lane;
+        const bool rep_wants = __shfl((int)want, (int)(j & 63), 64) != 0;
+        if (j != lane && rep_wants) want = false;
+    }
     const uint64_t b = __ballot(want);
     if (want) {
         a.rq[base + lane] = (int16_t)code;
@@ -1410,7 +1478,11 @@ __device__ inline void heavy_request(const ReplayArgs &a, int64_t base, int64_t 
     uint32_t n = 0;
     for (int64_t k0 = 0; k0 < C; k0 += 64) {
         const int64_t k = k0 + lane;
-        const bool w = k < C && want(k);
+        bool w = k < C && want(k);
+        if (w && a.alias) {
+            const int64_t j = (int64_t)a.alias[base + k] - base;
+            if (j != k && want(j)) w = false;
+        }
         const uint64_t b = __ballot(w);
         if (w) {
             a.rq[base + k] = (int16_t)code;
@@ -1536,8 +1608,9 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             const bool have = lane < C;
             const uint64_t key = have ? a.key[base + lane] : ~0ull;
             const uint32_t mask = have ? a.mask[base + lane] : 0u;
-            const int dc = have ? (int)a.dcap[base + lane] : 0;
-            const int vl = have ? (int)a.vlim[base + lane] : 0;
+            const uint32_t dv = have ? load_dv(a, base + lane) : 0u;
+            const int dc = dv_dc(dv);
+            const int vl = have ? dv_vl(dv) : 0;
             bool scored = false;
             uint64_t bmin = ~0ull;
             // bucket representative: first location of the same strand in the run of
@@ -1622,7 +1695,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         if (in_lds) {
             for (int64_t k = lane; k < C; k += 64) {
                 Lmask[k] = a.mask[base + k];
-                Ldv[k] = (uint32_t)a.dcap[base + k] | ((uint32_t)(uint16_t)a.vlim[base + k] << 16);
+                Ldv[k] = load_dv(a, base + k);
             }
             for (int w = lane; w < cap / 32; w += 64) Lsc[w] = 0;
         } else {
@@ -1631,8 +1704,8 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         for (int64_t k = lane; k < C; k += 64) a.bmin[base + k] = ~0ull;
         __builtin_amdgcn_wave_barrier();
         auto mask_at = [&](int64_t k) -> uint32_t { return in_lds ? Lmask[k] : a.mask[base + k]; };
-        auto dc_at = [&](int64_t k) -> int { return in_lds ? (int)(Ldv[k] & 0xFFFFu) : (int)a.dcap[base + k]; };
-        auto vl_at = [&](int64_t k) -> int { return in_lds ? (int)(int16_t)(Ldv[k] >> 16) : (int)a.vlim[base + k]; };
+        auto dc_at = [&](int64_t k) -> int { return dv_dc(in_lds ? Ldv[k] : load_dv(a, base + k)); };
+        auto vl_at = [&](int64_t k) -> int { return dv_vl(in_lds ? Ldv[k] : load_dv(a, base + k)); };
         auto scored_at = [&](int64_t k) -> bool {
             return in_lds ? ((Lsc[k >> 5] >> (k & 31)) & 1u) != 0 : a.scored[base + k] != 0;
         };
@@ -1808,7 +1881,7 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                     P[k] = (uint32_t)(key >> 1);
                     sbits |= (uint32_t)(key & 1) << k;
                     M[k] = a.mask[base + k];
-                    DV[k] = (uint32_t)a.dcap[base + k] | ((uint32_t)(uint16_t)a.vlim[base + k] << 16);
+                    DV[k] = load_dv(a, base + k);
                     BK[k] = P[k] / (uint32_t)a.rule.bucket;
                 }
             }
@@ -1914,7 +1987,7 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                 // the locations asked for (see k_replay), listed at the read's first slot
                 const int code = lane_class ? req_lim : (REQ_WAVE | req_lim);
                 const int lr = req_lim;
-                uint32_t n = 0;
+                uint32_t n = 0, wbits = 0;
 #pragma unroll
                 for (int k = 0; k < TINY_LOCS; k++) {
                     const int dc = (int)(DV[k] & 0xFFFFu), vl = (int)(int16_t)(DV[k] >> 16);
@@ -1922,7 +1995,17 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                     if (req_kind == 0) want = k == need_k;
                     else if (req_kind == 1) want = !((scored >> k) & 1u) && dc > vl && vl < lr;
                     else want = !((scored >> k) & 1u) && (M[k] & prefix) && dc > vl && vl < lr;
-                    if (k < C && want) {
+                    if (k < C && want) wbits |= 1u << k;
+                }
+#pragma unroll
+                for (int k = 0; k < TINY_LOCS; k++) {
+                    bool want = (wbits >> k) & 1u;
+                    if (want && a.alias) {
+                        // not when the location's representative asks in this round
+                        const int64_t j = (int64_t)a.alias[base + k] - base;
+                        if (j != k && j >= 0 && j < TINY_LOCS && ((wbits >> j) & 1u)) want = false;
+                    }
+                    if (want) {
                         a.rq[base + k] = (int16_t)code;
                         a.req_area[base + n] = (uint32_t)(base + k);
                         n++;
@@ -2006,8 +2089,10 @@ struct TilePred {
     const int64_t *ncand;
     int32_t lane_lmax, lane_kmax;
     bool want_long;
+    const uint32_t *alias;      // the lane tile's first verification takes representatives only
     __device__ bool operator()(uint32_t k) const {
         if ((int64_t)k >= *ncand) return false;
+        if (alias && !want_long && alias[k] != k) return false;
         const int L = len[gid(ps, cread[k])];
         const int K = min(dmax_for_length(rule, L) + rule.c - 1, ps.Kcap);
         return (L > lane_lmax || K > lane_kmax) == want_long;
@@ -2026,7 +2111,17 @@ struct FirstSeedsPred {
     const uint32_t *mask;
     const int64_t *ncand;
     uint32_t bits;
-    __host__ __device__ bool operator()(uint32_t k) const { return (int64_t)k < *ncand && (mask[k] & bits) != 0; }
+    const uint32_t *alias;      // representatives only, when set
+    __host__ __device__ bool operator()(uint32_t k) const {
+        return (int64_t)k < *ncand && (mask[k] & bits) != 0 && (!alias || alias[k] == k);
+    }
+};
+
+// Locations (below the chunk's count) that are their own exact-duplicate representative.
+struct RepPred {
+    const uint32_t *alias;
+    const int64_t *ncand;
+    __host__ __device__ bool operator()(uint32_t k) const { return (int64_t)k < *ncand && alias[k] == k; }
 };
 
 // Entries r of a read list (or reads [0, items) when it is null) with lo < count[r] <= hi.
@@ -2077,8 +2172,8 @@ struct Layout {
 // pool arrays per slot: hit 8, location key 8 + mask 4 (by read), compacted key 8 +
 // mask 4 + read 4, bucket minimum 8, capped distance 2, verified limit 2, scored flag 1,
 // verify routing lists / requests 4 + 4, requested limit 2
-constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 8 + 4 + 4 + 8 + 2 + 2 + 1 + 4 + 4 + 2;
-constexpr int POOL_ARRAYS = 13;
+constexpr size_t POOL_SLOT_BYTES = 8 + 8 + 4 + 8 + 4 + 4 + 8 + 2 + 2 + 1 + 4 + 4 + 2 + 4;
+constexpr int POOL_ARRAYS = 14;
 
 size_t scan_tmp_bytes(int64_t items) {
     size_t b = 0;
@@ -2380,6 +2475,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         uint8_t *scored;
         uint32_t *short_list, *long_list;
         int16_t *rq;
+        uint32_t *alias;
     };
     Worker wk[MAX_WORKERS];
     for (int w = 0; w < workers; w++) {
@@ -2414,6 +2510,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         W.short_list = (uint32_t *)carve(4 * (size_t)PS);
         W.long_list = (uint32_t *)carve(4 * (size_t)PS);
         W.rq = (int16_t *)carve(2 * (size_t)PS);
+        W.alias = (uint32_t *)carve(4 * (size_t)PS);
         if ((size_t)(pool - ws) > ws_bytes) return SNAP_ENOMEM;
     }
     int64_t steal_waves = 2048;
@@ -2496,6 +2593,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         uint8_t *scored = W.scored;
         uint32_t *short_list = W.short_list, *long_list = W.long_list;
         int16_t *rq = W.rq;
+        // representatives of exact-duplicate classes, when the index has classes
+        uint32_t *alias = (ix->d.rep != nullptr && ix->d.dup_w > 0) ? W.alias : nullptr;
+        unsigned long long *nalias = (unsigned long long *)(misc + 12);
         unsigned long long *steps_sum = (unsigned long long *)(misc + 6);
         unsigned long long *steps_first = (unsigned long long *)(misc + 7);
         int64_t *sel_n = misc + 20;   // selected counts: [2] reads to replay, [3] reads for the next pass, ...
@@ -2594,14 +2694,23 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 const int64_t *ncand = coff + nr;
                 const uint32_t *slist = nullptr;
                 const int64_t *nshort = ncand;
+                if (alias) {
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)nalias, 2, 0u);
+                    timed("dup_alias", st, [&] { hipLaunchKernelGGL(k_dup_alias, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, ix->d, key_c, cread, coff, lengths, ps, rule, ncand, alias, dcap, vlim, steps, nalias); });
+                }
                 if (!all_lane) {
                     int64_t *rc64 = (int64_t *)route_cnt;
-                    HIP_OK(select_idx(sel_tmp, sel_tb, total, TilePred{cread, lengths, ps, rule, ncand, lane_lmax, LANE_KMAX, false},
+                    HIP_OK(select_idx(sel_tmp, sel_tb, total, TilePred{cread, lengths, ps, rule, ncand, lane_lmax, LANE_KMAX, false, alias},
                                       short_list, rc64, st));
-                    HIP_OK(select_idx(sel_tmp, sel_tb, total, TilePred{cread, lengths, ps, rule, ncand, lane_lmax, LANE_KMAX, true},
+                    HIP_OK(select_idx(sel_tmp, sel_tb, total, TilePred{cread, lengths, ps, rule, ncand, lane_lmax, LANE_KMAX, true, nullptr},
                                       long_list, rc64 + 1, st));
                     slist = short_list;
                     nshort = rc64;
+                } else if (alias && !(verify_seeds > 0 && verify_seeds < NSp)) {
+                    // the first verification takes the representatives only
+                    HIP_OK(select_idx(sel_tmp, sel_tb, total, RepPred{alias, ncand}, short_list, sel_n + 5, st));
+                    slist = short_list;
+                    nshort = sel_n + 5;
                 }
                 VerifyArgs va{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread, ncand,
                               rule, RW, TW, dcap, vlim, steps, slist, nshort};
@@ -2634,7 +2743,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                         const uint32_t bits = (1u << verify_seeds) - 1u;
                         const unsigned mb = (unsigned)((total + 255) / 256);
                         timed("mark", st, [&] { hipLaunchKernelGGL(k_mark_late, dim3(mb), dim3(256), 0, st, mask_c, ncand, bits, dcap, vlim, steps); });
-                        HIP_OK(select_idx(sel_tmp, sel_tb, total, FirstSeedsPred{mask_c, ncand, bits}, short_list, sel_n + 5, st));
+                        HIP_OK(select_idx(sel_tmp, sel_tb, total, FirstSeedsPred{mask_c, ncand, bits, alias}, short_list, sel_n + 5, st));
                         va.list = short_list;
                         va.nlist_ptr = sel_n + 5;
                     }
@@ -2657,7 +2766,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
-                          rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax,
+                          alias, rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax,
                           pos, strand, dist, second, call};
             const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
             // reads with up to TINY_LOCS locations replay a lane each; the others, a wave
@@ -2767,13 +2876,14 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             HIP_OK(hipGetLastError());
             if (g_prof_on) {
                 // counters for the roofline: one extra wait per chunk, profiling only
-                unsigned long long zero = 0, ssum = 0, sfirst = 0;
+                unsigned long long zero = 0, ssum = 0, sfirst = 0, nal = 0;
                 int64_t ncand = 0;
                 if (total > 0) {
                     HIP_OK(hipMemcpyAsync(steps_sum, &zero, 8, hipMemcpyHostToDevice, st));
                     hipLaunchKernelGGL(k_sum_u32, dim3(256), dim3(256), 0, st, steps, coff + nr, steps_sum);
                     HIP_OK(hipMemcpyAsync(&ssum, steps_sum, 8, hipMemcpyDeviceToHost, st));
                     HIP_OK(hipMemcpyAsync(&sfirst, steps_first, 8, hipMemcpyDeviceToHost, st));
+                    if (alias) HIP_OK(hipMemcpyAsync(&nal, nalias, 8, hipMemcpyDeviceToHost, st));
                 }
                 HIP_OK(hipMemcpyAsync(&ncand, coff + nr, 8, hipMemcpyDeviceToHost, st));
                 HIP_OK(hipStreamSynchronize(st));
@@ -2785,6 +2895,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 g_ctr.locations += ncand;
                 g_ctr.lv_steps += (int64_t)ssum;
                 g_ctr.lv_steps_first += (int64_t)sfirst;
+                g_ctr.dup_aliases += (int64_t)nal;
                 if (ridx) g_ctr.second_pass_reads += nr;
             }
             r0 += nr;

@@ -367,6 +367,7 @@ extern "C" int snap_index_free(snap_index *ix) {
     if (ix->alloc_gmask) (void)hipFree(ix->alloc_gmask);
     if (ix->alloc_table) (void)hipFree(ix->alloc_table);
     if (ix->alloc_pos) (void)hipFree(ix->alloc_pos);
+    if (ix->alloc_rep) (void)hipFree(ix->alloc_rep);
     (void)hipSetDevice(dev);
     delete ix;
     return SNAP_OK;
@@ -429,6 +430,7 @@ extern "C" int snap_index_info(const snap_index *ix, snap_index_sizes *info) {
     info->position_entries = ix->position_entries;
     info->device_bytes = ix->device_bytes;
     info->device = ix->device;
+    info->dup_window = ix->d.rep ? ix->d.dup_w : 0;
     return SNAP_OK;
 }
 

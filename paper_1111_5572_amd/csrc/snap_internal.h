@@ -37,6 +37,8 @@ struct DevIndex {
     int32_t log2_buckets;
     int32_t s;
     int32_t stride;              // windows at positions q with q % stride == 0 are indexed
+    const uint32_t *rep;         // exact-duplicate class of each position's dup_w-base window, or null
+    int32_t dup_w;
 };
 
 // 64-bit finalizer (MurmurHash3 fmix64, Appleby): spreads a seed code over the table.
@@ -89,4 +91,7 @@ struct snap_index {
     uint64_t position_entries;
     uint64_t device_bytes;
     void *alloc_gcode, *alloc_gmask, *alloc_table, *alloc_pos;
+    void *alloc_rep;             // duplicate classes (snap_index_dup_classes), or null
+    uint64_t rep_bytes;
+    uint64_t dup_collisions;     // hash collisions the class build resolved by comparison
 };
