@@ -120,7 +120,7 @@ int snap_index_build_strided(const uint8_t *genome, uint64_t len, int32_t seed_l
  * with L + d_max(L) + c - 1 <= window, one location per class and strand among the read's
  * locations and answers the others from it (their text windows are identical, so every
  * edit distance is); outputs do not change. Calling it again replaces the classes.
- * Device memory: 4 bytes per base kept with the index; about 24 bytes per window more
+ * Device memory: 4 bytes and 1 bit per base kept with the index; about 24 bytes per window more
  * while building. The current device must be the index's. Errors: SNAP_EINVAL (NULL
  * index, window < 1, another device), SNAP_ENOMEM, SNAP_EDEVICE. */
 int snap_index_dup_classes(snap_index *ix, int32_t window, void *stream);

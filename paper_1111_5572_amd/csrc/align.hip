@@ -1272,10 +1272,12 @@ __global__ __launch_bounds__(64) void k_verify_steal(StealArgs a) {
 // not its own: the two W-base windows are identical, so every seed that hits k hits it at
 // the same offset, with the same counts (with a strided index the other position may not
 // be indexed; then k stays its own). k itself otherwise. An alias is left unverified: its
-// representative's results answer it (the replays take them). *nalias counts aliases.
-__global__ void k_dup_alias(DevIndex ix, const uint64_t *key, const uint32_t *cread, const int64_t *coff,
-                            const int32_t *len, Pass ps, Rule rule, const int64_t *ncand_ptr, uint32_t *alias,
-                            uint16_t *dcap, int16_t *vlim, uint32_t *steps, unsigned long long *nalias) {
+// representative's results answer it (the replays take them). *nalias (profiling only,
+// else null) counts aliases, one atomic add per workgroup.
+__global__ __launch_bounds__(256) void k_dup_alias(DevIndex ix, const uint64_t *key, const uint32_t *cread,
+                                                   const int64_t *coff, const int32_t *len, Pass ps, Rule rule,
+                                                   const int64_t *ncand_ptr, uint32_t *alias, uint16_t *dcap,
+                                                   int16_t *vlim, uint32_t *steps, unsigned long long *nalias) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = *ncand_ptr;
     uint32_t al = (uint32_t)k;
@@ -1285,7 +1287,7 @@ __global__ void k_dup_alias(DevIndex ix, const uint64_t *key, const uint32_t *cr
         if (L + dmax_for_length(rule, L) + rule.c - 1 <= ix.dup_w) {
             const uint64_t kk = key[k];
             const uint64_t p = kk >> 1;
-            const uint64_t h = ix.rep[p];
+            const uint64_t h = ((ix.repbits[p >> 5] >> (p & 31)) & 1u) ? ix.rep[p] : p;
             if (h != p) {
                 const uint64_t want = (h << 1) | (kk & 1);
                 int64_t lo = coff[r], hi = coff[r + 1];
@@ -1303,8 +1305,16 @@ __global__ void k_dup_alias(DevIndex ix, const uint64_t *key, const uint32_t *cr
             if (steps) steps[k] = 0;
         }
     }
-    const uint64_t b = __ballot(k < n && al != (uint32_t)k);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(nalias, (unsigned long long)__popcll(b));
+    if (nalias) {
+        __shared__ uint32_t wsum[4];
+        const uint64_t b = __ballot(k < n && al != (uint32_t)k);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+            if (t) atomicAdd(nalias, (unsigned long long)t);
+        }
+    }
 }
 
 __global__ void k_mark_late(const uint32_t *mask, const int64_t *ncand_ptr, uint32_t bits, uint16_t *dcap,
@@ -2696,7 +2706,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 const int64_t *nshort = ncand;
                 if (alias) {
                     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)nalias, 2, 0u);
-                    timed("dup_alias", st, [&] { hipLaunchKernelGGL(k_dup_alias, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, ix->d, key_c, cread, coff, lengths, ps, rule, ncand, alias, dcap, vlim, steps, nalias); });
+                    timed("dup_alias", st, [&] { hipLaunchKernelGGL(k_dup_alias, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, ix->d, key_c, cread, coff, lengths, ps, rule, ncand, alias, dcap, vlim, steps, g_prof_on ? nalias : nullptr); });
                 }
                 if (!all_lane) {
                     int64_t *rc64 = (int64_t *)route_cnt;

@@ -20,7 +20,8 @@
 //      listed and each compared with the earlier listed members of its run: the first
 //      identical one is its class, else it is its own. No hash collision is trusted.
 // Memory while building: 24 bytes per window (keys and positions, double buffered),
-// freed before returning; the class array (4 bytes per base) stays with the index.
+// freed before returning; the class array (4 bytes per base) and a bit map of the
+// positions whose class is another position (1 bit per base) stay with the index.
 
 #include <algorithm>
 #include <new>
@@ -143,6 +144,20 @@ __global__ void k_collisions(const uint32_t *gcode, const uint32_t *gmask, const
     }
 }
 
+// Bit q of the map: position q's class is another position (rep[q] != q). The alignment
+// reads this map first (32 times smaller than the class array, mostly cache-resident)
+// and the class array only where the bit is set.
+__global__ void k_dup_bits(const uint32_t *rep, uint64_t G, uint32_t *bits, uint64_t nwords) {
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t v = 0;
+        for (int b = 0; b < 32; b++) {
+            const uint64_t q = w * 32 + (uint64_t)b;
+            if (q < G && rep[q] != (uint32_t)q) v |= 1u << b;
+        }
+        bits[w] = v;
+    }
+}
+
 struct Buf {
     void *p = nullptr;
     ~Buf() { if (p) (void)hipFree(p); }
@@ -226,12 +241,21 @@ int build_classes(snap_index *ix, int64_t W, hipStream_t st) {
         DEV_OK(hipStreamSynchronize(st));
         ix->dup_collisions = 0;
     }
+    const uint64_t nwords = (G + 31) / 32;
+    Buf bits;
+    RC_OK(bits.alloc(nwords * 4));
+    hipLaunchKernelGGL(k_dup_bits, dim3(8192), dim3(256), 0, st, (const uint32_t *)rep.p, G, (uint32_t *)bits.p, nwords);
+    DEV_OK(hipGetLastError());
+    DEV_OK(hipStreamSynchronize(st));
     if (ix->alloc_rep) (void)hipFree(ix->alloc_rep);
+    if (ix->alloc_repbits) (void)hipFree(ix->alloc_repbits);
     ix->alloc_rep = rep.release();
+    ix->alloc_repbits = bits.release();
     ix->d.rep = (const uint32_t *)ix->alloc_rep;
+    ix->d.repbits = (const uint32_t *)ix->alloc_repbits;
     ix->d.dup_w = (int32_t)W;
-    ix->device_bytes += ix->rep_bytes ? 0 : G * 4;
-    ix->rep_bytes = G * 4;
+    ix->device_bytes += ix->rep_bytes ? 0 : G * 4 + nwords * 4;
+    ix->rep_bytes = G * 4 + nwords * 4;
     return SNAP_OK;
 }
 

@@ -368,6 +368,7 @@ extern "C" int snap_index_free(snap_index *ix) {
     if (ix->alloc_table) (void)hipFree(ix->alloc_table);
     if (ix->alloc_pos) (void)hipFree(ix->alloc_pos);
     if (ix->alloc_rep) (void)hipFree(ix->alloc_rep);
+    if (ix->alloc_repbits) (void)hipFree(ix->alloc_repbits);
     (void)hipSetDevice(dev);
     delete ix;
     return SNAP_OK;

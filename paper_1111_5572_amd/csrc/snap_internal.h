@@ -38,6 +38,7 @@ struct DevIndex {
     int32_t s;
     int32_t stride;              // windows at positions q with q % stride == 0 are indexed
     const uint32_t *rep;         // exact-duplicate class of each position's dup_w-base window, or null
+    const uint32_t *repbits;     // bit q: rep[q] != q
     int32_t dup_w;
 };
 
@@ -92,6 +93,7 @@ struct snap_index {
     uint64_t device_bytes;
     void *alloc_gcode, *alloc_gmask, *alloc_table, *alloc_pos;
     void *alloc_rep;             // duplicate classes (snap_index_dup_classes), or null
+    void *alloc_repbits;
     uint64_t rep_bytes;
     uint64_t dup_collisions;     // hash collisions the class build resolved by comparison
 };
