@@ -94,6 +94,11 @@ def bench_accuracy(args, w, dev):
         snapgpu.set_tuning(*tuning)
     log(f"schedule {tuning or 'library default'}")
     stream = torch.cuda.current_stream()
+    import oracle
+    t = time.time()
+    oix = oracle.Index(g, w.params.seed_len, threads=oracle_threads())
+    log(f"oracle index in {time.time() - t:.1f}s")
+    rng = np.random.default_rng(9)
     rows = []
     out = None
     for h in HMAX_SWEEP:
@@ -107,11 +112,21 @@ def bench_accuracy(args, w, dev):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / max(1, args.steps)
-        row = {"h_max": h, **accuracy_of(out.numpy(), reads), "reads_per_s": round(n / (ms / 1e3), 1),
-               "ms_per_step": round(ms, 3)}
+        got = out.numpy()
+        idx = np.unique(rng.integers(0, n, min(n, 3000)))
+        res = oix.align_reads(reads.subset(idx), oracle.params_from(replace(w.params, max_hits=h, d_max=8)),
+                              threads=oracle_threads())
+        mism = sum(int(np.count_nonzero(np.asarray(a)[idx].astype(np.int64) != np.asarray(b).astype(np.int64)))
+                   for a, b in zip(got, res.fields()))
+        if mism:
+            print(json.dumps({"error": f"h_max {h}: GPU differs from the oracle on {mism} fields"}), flush=True)
+            sys.exit(1)
+        row = {"h_max": h, **accuracy_of(got, reads), "reads_per_s": round(n / (ms / 1e3), 1),
+               "ms_per_step": round(ms, 3), "oracle_sample": int(len(idx))}
         log(f"h_max {h}: {row}")
         rows.append(row)
     gix.close()
+    oix.close()
     print(json.dumps({"metric": "h_max trade-off", "unit": "aligned %, error %, reads/s", "n_gpus": 1,
                       "steps": max(1, args.steps), "data": "synthetic (seeded genome and simulated reads)",
                       "config": {"workload": w.name, "genome_bases": len(g), "reads": n, "read_len": 125,
@@ -119,6 +134,88 @@ def bench_accuracy(args, w, dev):
                                  "conf_c": w.params.conf_c, "seed_len": w.params.seed_len,
                                  "correct": "same strand, |pos - source| <= 32",
                                  "schedule": list(tuning) if tuning else None},
+                      "rows": rows}), flush=True)
+
+
+# Section 2's tables: (table, read length, error rate, reads, share of erroneous bases in indels)
+ACCURACY_GRID = [
+    ("Table 1", 100, 0.02, 200_000, 0.1), ("Table 1", 100, 0.05, 200_000, 0.1), ("Table 1", 100, 0.10, 200_000, 0.1),
+    ("Table 1", 200, 0.02, 200_000, 0.1), ("Table 1", 200, 0.05, 200_000, 0.1), ("Table 1", 200, 0.10, 200_000, 0.1),
+    ("Table 2", 1000, 0.02, 20_000, 0.2), ("Table 2", 1000, 0.05, 20_000, 0.2), ("Table 2", 1000, 0.10, 20_000, 0.2),
+    ("Table 2", 10000, 0.02, 2_000, 0.2), ("Table 2", 10000, 0.05, 2_000, 0.2), ("Table 2", 10000, 0.10, 1_000, 0.2),
+]
+INDEL_MEAN_LEN = 57 / 31   # mean of the truncated geometric(1/2) indel length on 1..5
+
+
+def grid_dmax(L, err):
+    """d_max of a grid cell: 1.5 times the expected edits, at least 8, within the largest
+    limit the verify kernels take (d_max + c - 1 <= 1023)."""
+    return int(min(1022, max(8, -(-15 * err * L // 10))))
+
+
+def bench_accuracy_grid(args, w, dev):
+    """The metrics of Section 2's Tables 1 and 2 on the stand-in genome: for 100 / 200 bp
+    reads (Table 1) and 1 kb / 10 kb reads (Table 2, 20% of the erroneous bases in indels)
+    at 2 / 5 / 10% errors, the share of reads aligned confidently (a single call), the
+    share of those more than 32 bases from their source or on the other strand, and
+    reads/s; each cell's GPU outputs are checked bit-exact on a seeded sample against the
+    oracle."""
+    import torch
+    import synth
+    import oracle
+    import paper_1111_5572_amd as snapgpu
+    from dataclasses import replace
+    g = w.make_genome()
+    gix = build_index(g, w.params.seed_len)
+    t = time.time()
+    oix = oracle.Index(g, w.params.seed_len, threads=oracle_threads())
+    log(f"oracle index in {time.time() - t:.1f}s")
+    rng = np.random.default_rng(8)
+    rows = []
+    for k, (table, L, err, n, indel_share) in enumerate(ACCURACY_GRID):
+        n = max(1, n // max(1, args.grid_scale))
+        p_indel = err * indel_share / INDEL_MEAN_LEN
+        model = synth.ReadModel(len_mode=0, len_a=L, len_b=L, p_sub=err * (1 - indel_share), p_indel=p_indel,
+                                indel_max=5)
+        reads = synth.simulate_reads(g, n, 200 + k, model)
+        d_max = grid_dmax(L, err)
+        wp = replace(w.params, d_max=d_max, d_max_pct=0)
+        p = snapgpu.params_from(wp)
+        rb = torch.from_numpy(reads.bases).to(dev)
+        ln = torch.from_numpy(reads.lengths).to(dev)
+        out = snapgpu.align(gix, rb, ln, d_max, p, max_len=L)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps)):
+            out = snapgpu.align(gix, rb, ln, d_max, p, out=out, max_len=L)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / max(1, args.steps)
+        got = out.numpy()
+        # oracle sample: bit-exact on all five outputs
+        ns = int(min(n, 2000 if L <= 200 else (200 if L <= 1000 else 16)))
+        idx = np.unique(rng.integers(0, n, ns))
+        res = oix.align_reads(reads.subset(idx), oracle.params_from(wp), threads=oracle_threads())
+        mism = sum(int(np.count_nonzero(np.asarray(a)[idx].astype(np.int64) != np.asarray(b).astype(np.int64)))
+                   for a, b in zip(got, res.fields()))
+        if mism:
+            print(json.dumps({"error": f"{table} L={L} err={err}: GPU differs from the oracle on {mism} fields"}),
+                  flush=True)
+            sys.exit(1)
+        row = {"table": table, "read_len": L, "error_rate": err, "reads": n, "d_max": d_max,
+               **accuracy_of(got, reads), "reads_per_s": round(n / sec, 1), "oracle_sample": int(len(idx))}
+        log(f"{row}")
+        rows.append(row)
+        del rb, ln, out
+    gix.close()
+    oix.close()
+    print(json.dumps({"metric": "aligned and error rates (Section 2's tables)", "unit": "%, reads/s", "n_gpus": 1,
+                      "steps": max(1, args.steps), "data": "synthetic (seeded genome and simulated reads)",
+                      "config": {"workload": w.name, "genome_bases": len(g), "seed_len": w.params.seed_len,
+                                 "conf_c": w.params.conf_c, "max_hits": w.params.max_hits,
+                                 "errors": "Table 1: 90% of erroneous bases substituted, 10% in indels of 1-5; "
+                                           "Table 2: 80% / 20%",
+                                 "d_max": "min(1022, max(8, ceil(1.5 * error rate * L)))",
+                                 "correct": "same strand, |pos - source| <= 32"},
                       "rows": rows}), flush=True)
 
 
@@ -260,7 +357,7 @@ def oracle_threads():
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def oracle_check(g, reads, w, got, seconds, single_seconds=4.0):
+def oracle_check(g, reads, w, got, seconds, single_seconds=4.0, probe=4000, probe1=500):
     """The oracle on a seeded sample of the batch sized to about `seconds` on the host
     cores: the GPU outputs of the sample must equal it on all five fields (else the run
     stops with an error). Returns (cpu_baseline entry, Algorithm 1's own work per read on
@@ -283,7 +380,7 @@ def oracle_check(g, reads, w, got, seconds, single_seconds=4.0):
         return res, time.perf_counter() - t0
 
     # one thread on a small sample (the paper quotes one core's rate)
-    idx1 = sample(500)
+    idx1 = sample(probe1)
     res1, dt1 = run(idx1, 1)
     n1 = int(min(reads.n, max(len(idx1), len(idx1) / max(dt1, 1e-9) * single_seconds)))
     if n1 > len(idx1):
@@ -291,7 +388,7 @@ def oracle_check(g, reads, w, got, seconds, single_seconds=4.0):
         res1, dt1 = run(idx1, 1)
     single = round(len(idx1) / dt1, 1)
     # all threads, sized from a probe
-    idx = sample(4000)
+    idx = sample(probe)
     res, dt = run(idx, threads)
     n_s = int(min(reads.n, max(len(idx), len(idx) / max(dt, 1e-9) * seconds)))
     if n_s > len(idx):
@@ -408,12 +505,15 @@ def bench_batched(args, w, dev):
     for _ in range(args.warmup):
         snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True, tuning=tuning)
     torch.cuda.synchronize()
-    snapgpu.profile_begin()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True, tuning=tuning)
     torch.cuda.synchronize()
     batched_s = (time.perf_counter() - t0) / args.steps
+    # one profiled step of its own: per-kernel times and counters
+    snapgpu.profile_begin()
+    snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True, tuning=tuning)
+    torch.cuda.synchronize()
     kern = snapgpu.profile_end()
     ctr = snapgpu.profile_counters()
     got = out.numpy()
@@ -424,7 +524,8 @@ def bench_batched(args, w, dev):
     if not same:
         print(json.dumps({"error": "batched and per-bucket plain outputs differ"}), flush=True)
         sys.exit(1)
-    cpu, method = (None, None) if args.no_cpu_baseline else oracle_check(g, reads, w, got, args.cpu_seconds)
+    cpu, method = (None, None) if args.no_cpu_baseline else oracle_check(g, reads, w, got, args.cpu_seconds,
+                                                                             probe=64, probe1=8)
     roofline = roofline_of(kern, ctr, method=method)
     roofline["traffic"] = None
     calls = np.bincount(got[4].astype(np.int64), minlength=3)
@@ -445,8 +546,8 @@ def bench_batched(args, w, dev):
         "index_build_s": round(index_s, 2), "index_build": "host" if INDEX_ON_HOST else "device",
         "index_device_bytes": sizes["device_bytes"],
         "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
-        "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
-        "counters_per_step": {k: v // max(args.steps, 1) for k, v in ctr.items()},
+        "kernel_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()},
+        "counters_per_step": ctr,
         "roofline": roofline,
         # the two phases the method hinges on: gather (HBM-bound) and verify (VALU-bound)
         "phases": phases_of(kern, ctr, method),
@@ -493,11 +594,15 @@ def bench_served(args, w, dev):
         cursor[0] = i + k
         return pool.bases[offs[i]:offs[i + k]], pool.lengths[i:i + k]
 
-    def run(n_req, arrivals=None, sizes=None):
+    kept = []   # (bases, lengths, outputs) of sampled requests, for the oracle check
+
+    def run(n_req, arrivals=None, sizes=None, keep_every=0):
         """Submit n_req requests (open loop at `arrivals` seconds, or back to back),
-        poll them all; returns (elapsed, reads, latencies)."""
+        poll them all; returns (elapsed, reads, latencies). With keep_every, the outputs
+        of every keep_every-th request of at most 300 reads are kept."""
         done = {}
         tickets = []
+        inputs = {}
         lock = threading.Lock()
         stop = [False]
 
@@ -510,6 +615,8 @@ def bench_served(args, w, dev):
                     r = srv.poll(tk)
                     if r is not None:
                         done[tk] = r[5]
+                        if tk in inputs:
+                            kept.append((*inputs[tk], r[:5]))
                 if finished:
                     return
                 time.sleep(0.0002)
@@ -534,6 +641,8 @@ def bench_served(args, w, dev):
                     time.sleep(0.0005)
             nreads += len(l)
             with lock:
+                if keep_every and q % keep_every == 0 and len(l) <= 300:
+                    inputs[tk] = (np.array(b), np.array(l))
                 tickets.append((tk, len(l)))
         with lock:
             stop[0] = True
@@ -543,9 +652,9 @@ def bench_served(args, w, dev):
         return elapsed, nreads, lat
 
     rng_sizes = lambda n, seed: synth.arrivals(n, seed, 1.0)[1]
-    nq = args.steps * 100
+    nq = max(args.requests, 1)
     run(max(20, nq // 10), sizes=rng_sizes(max(20, nq // 10), 104))   # warm-up
-    el, nr, lat = run(nq, sizes=rng_sizes(nq, 105))
+    el, nr, lat = run(nq, sizes=rng_sizes(nq, 105), keep_every=20)
     sat = nr / el
     log(f"saturated: {nq} requests, {nr} reads in {el:.2f}s = {sat:,.0f} reads/s; p50 {np.median(lat)*1e3:.1f} ms")
     levels = {}
@@ -554,8 +663,10 @@ def bench_served(args, w, dev):
         rate = load * sat / float(np.mean(sizes))
         arr, _ = synth.arrivals(nq, 107, rate)
         el, nr, lat = run(nq, arrivals=arr, sizes=sizes)
-        levels[f"{int(load * 100)}%"] = {"offered_reads_per_s": round(load * sat, 1),
+        offered = nr / float(arr[-1]) if len(arr) and arr[-1] > 0 else load * sat
+        levels[f"{int(load * 100)}%"] = {"offered_reads_per_s": round(offered, 1),
                                          "achieved_reads_per_s": round(nr / el, 1),
+                                         "kept_up": bool(nr / el >= 0.95 * offered),
                                          "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                                          "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
                                          "requests": nq}
@@ -563,6 +674,29 @@ def bench_served(args, w, dev):
     st = srv.stats()
     srv.close()
     gix.close()
+    # the outputs of sampled requests against the oracle, bit for bit
+    checked = None
+    if not args.no_cpu_baseline and kept:
+        import oracle
+        import synth as sy
+        t = time.time()
+        oix = oracle.Index(g, w.params.seed_len, threads=oracle_threads())
+        op = oracle.params_from(w.params)
+        nreq = nrd = 0
+        for bases, lens, outs in kept[:12]:
+            offs_ = np.zeros(len(lens) + 1, np.int64)
+            np.cumsum(lens, out=offs_[1:])
+            res = oix.align(bases, offs_, lens, op, threads=oracle_threads())
+            mism = sum(int(np.count_nonzero(np.asarray(a).astype(np.int64) != np.asarray(b).astype(np.int64)))
+                       for a, b in zip(outs, res.fields()))
+            if mism:
+                print(json.dumps({"error": f"a served request differs from the oracle on {mism} fields"}), flush=True)
+                sys.exit(1)
+            nreq += 1
+            nrd += len(lens)
+        oix.close()
+        checked = {"requests": nreq, "reads": nrd, "bit_exact": True, "seconds": round(time.time() - t, 1)}
+        log(f"oracle check of served requests: {checked}")
     line = {
         "metric": "reads aligned/s", "value": round(sat, 1), "unit": "reads/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
@@ -570,7 +704,7 @@ def bench_served(args, w, dev):
         "config": {"workload": "served", "genome_bases": len(g), "read_pool": pool.n,
                    "request_reads": "floor(10^(4u))", "read_len": "100 bp-10 kb log-uniform",
                    "slots": st["slots"], "slot_device_bytes": st["slot_device_bytes"]},
-        "latency": levels, "server": st, "roofline": None, "cpu_baseline": None,
+        "latency": levels, "server": st, "roofline": None, "cpu_baseline": None, "oracle_check": checked,
     }
     print(json.dumps(line), flush=True)
 
@@ -805,6 +939,7 @@ def main():
     ap.add_argument("--workload", default="human")
     ap.add_argument("--reads", type=int, default=0, help="override the read count (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--requests", type=int, default=2000, help="served workload: requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "verify_traffic_mid.txt"),
                     help="counter summary giving the dominant kernel's HBM bytes per launch")
@@ -817,6 +952,9 @@ def main():
                     help="index only the windows at multiples of this stride (1, 2 or 4; device build)")
     ap.add_argument("--accuracy", action="store_true",
                     help="h_max sweep: aligned / error rates and reads/s for 125 bp reads at 2%% errors")
+    ap.add_argument("--accuracy-grid", action="store_true",
+                    help="Section 2's tables: aligned / error rates and reads/s over read lengths and error rates")
+    ap.add_argument("--grid-scale", type=int, default=1, help="divide the grid's read counts by this")
     ap.add_argument("--index-only", action="store_true",
                     help="time the index build of the workload's genome (--steps builds) and stop")
     ap.add_argument("--retune", action="store_true",
@@ -863,6 +1001,8 @@ def main():
         return bench_index(args, w)
     if args.accuracy:
         return bench_accuracy(args, w, dev)
+    if args.accuracy_grid:
+        return bench_accuracy_grid(args, w, dev)
     if args.workload == "batched":
         return bench_batched(args, w, dev)
     if args.workload == "served":

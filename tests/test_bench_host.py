@@ -117,3 +117,12 @@ def test_tuning_table_lookup(tmp_path):
     assert autotune.lookup(np.full(10, 5000, np.int32), batched=False, path=str(table)) is None
     # the committed table has the mid entry the benchmark uses
     assert autotune.lookup(lens, batched=False) is not None
+
+
+def test_accuracy_grid_dmax(bench):
+    # 1.5 times the expected edits, at least 8, at most the largest limit minus c - 1
+    assert bench.grid_dmax(100, 0.02) == 8
+    assert bench.grid_dmax(100, 0.10) == 15
+    assert bench.grid_dmax(1000, 0.05) == 75
+    assert bench.grid_dmax(10000, 0.10) == 1022
+    assert [row[1] for row in bench.ACCURACY_GRID].count(10000) == 3
