@@ -219,6 +219,38 @@ def bench_accuracy_grid(args, w, dev):
                       "rows": rows}), flush=True)
 
 
+def bench_gather(args, dev):
+    """The random-line gather ceiling: 32 / 64 / 128-byte lines read at pseudo-random
+    places of a `--gather-gb` GB device buffer (the probe's bucket lines, the position
+    reads), GB/s of lines delivered, beside the 8 TB/s HBM peak."""
+    import torch
+    import paper_1111_5572_amd as snapgpu
+    nbytes = int(args.gather_gb * (1 << 30)) // 128 * 128
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    threads = 1 << 22
+    sink = torch.empty(threads, dtype=torch.int32, device=dev)
+    rows = []
+    for line in (32, 64, 128):
+        rounds = 64
+        snapgpu.debug_gather_lines(buf, nbytes, line, rounds, threads, 1, sink)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for r in range(reps):
+            snapgpu.debug_gather_lines(buf, nbytes, line, rounds, threads, 2 + r, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        moved = threads * rounds * 16
+        row = {"line_bytes": line, "bytes_per_launch": moved, "ms": round(sec * 1e3, 3),
+               "gb_per_s": round(moved / sec / 1e9, 1), "frac_of_hbm_peak": round(moved / sec / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"gather {row}")
+        rows.append(row)
+    print(json.dumps({"metric": "random-line gather ceiling", "unit": "GB/s", "n_gpus": 1,
+                      "config": {"buffer_bytes": nbytes, "threads": threads, "rounds": 64}, "rows": rows}), flush=True)
+
+
 def bench_index(args, w):
     """The index build alone: the workload's genome indexed --steps times (after one
     untimed build); one JSON line with the mean build time (host-to-device copy of the
@@ -955,6 +987,8 @@ def main():
     ap.add_argument("--accuracy-grid", action="store_true",
                     help="Section 2's tables: aligned / error rates and reads/s over read lengths and error rates")
     ap.add_argument("--grid-scale", type=int, default=1, help="divide the grid's read counts by this")
+    ap.add_argument("--gather-gb", type=float, default=0.0,
+                    help="only run the random-line gather microbenchmark over a buffer of this many GB")
     ap.add_argument("--index-only", action="store_true",
                     help="time the index build of the workload's genome (--steps builds) and stop")
     ap.add_argument("--retune", action="store_true",
@@ -997,6 +1031,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.copy_bytes} bytes 3 times, equal: {bool(torch.equal(src, dst))}")
         return
+    if args.gather_gb:
+        return bench_gather(args, dev)
     if args.index_only:
         return bench_index(args, w)
     if args.accuracy:

@@ -40,6 +40,16 @@ int32_t snap_debug_seed_offsets(int32_t L, int32_t s, int32_t n, int32_t *out);
  */
 int snap_debug_copy(const void *src, void *dst, uint64_t bytes, void *stream);
 
+/* Random-line gather microbenchmark (the access pattern of the seed probe and the
+ * position reads): `threads` threads (a multiple of 256 and of line_bytes / 16) read, in
+ * groups of line_bytes / 16 lanes, one line_bytes-byte line (32, 64 or 128) at a
+ * pseudo-random line-aligned place of the device buffer `buf` (`bytes` long, 128-byte
+ * aligned), `rounds` times each; each thread writes one uint32 to device `sink`.
+ * Algorithmic bytes: threads * rounds * 16. Async on `stream`. Errors: SNAP_EINVAL,
+ * SNAP_EDEVICE. */
+int snap_debug_gather_lines(const void *buf, uint64_t bytes, int32_t line_bytes, int32_t rounds, uint64_t threads,
+                            uint64_t seed, void *sink, void *stream);
+
 /* Copy one device array of an index to host memory (for checks): which = 0 packed
  * genome (uint32 words), 1 N mask (uint32 words), 2 table (two uint64 per slot),
  * 3 positions (uint32). `bytes` must equal the array's size (from snap_index_info: G,

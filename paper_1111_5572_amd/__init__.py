@@ -180,6 +180,8 @@ def lib():
         L.snap_server_stats.restype = ctypes.c_int
         L.snap_server_destroy.argtypes = [P]
         L.snap_server_destroy.restype = ctypes.c_int
+        L.snap_debug_gather_lines.argtypes = [P, u64, i32, i32, u64, u64, P, P]
+        L.snap_debug_gather_lines.restype = ctypes.c_int
         L.snap_debug_copy.argtypes = [P, P, u64, P]
         L.snap_debug_copy.restype = ctypes.c_int
         _lib = L
@@ -483,6 +485,11 @@ def profile_counters() -> dict:
     c = Counters()
     _check(lib().snap_profile_counters(ctypes.byref(c)), "snap_profile_counters")
     return {n: int(getattr(c, n)) for n, _ in c._fields_}
+
+
+def debug_gather_lines(buf, nbytes: int, line_bytes: int, rounds: int, threads: int, seed: int, sink, stream=None):
+    _check(lib().snap_debug_gather_lines(buf.data_ptr(), nbytes, line_bytes, rounds, threads, seed, sink.data_ptr(),
+                                         _stream_ptr(stream)), "snap_debug_gather_lines")
 
 
 def debug_copy(src, dst, nbytes: int, stream=None):

@@ -3094,6 +3094,40 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restric
         dst[i] = src[i];
 }
 
+// Random-line gather (the access pattern of the probe and the position reads): every
+// group of `line / 16` lanes reads one `line`-byte line at a pseudo-random line-aligned
+// place of the buffer (16 bytes a lane, one coalesced access), `rounds` times; the lines'
+// words are summed so the loads stay, and each thread writes its sum once.
+__global__ __launch_bounds__(256) void k_gather_lines(const uint4 *buf, uint64_t nlines, int lanes_per_line,
+                                                      int rounds, uint64_t seed, uint32_t *sink) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t grp = t / (uint64_t)lanes_per_line;
+    const int sub = (int)(t % (uint64_t)lanes_per_line);
+    uint32_t acc = 0;
+    for (int i = 0; i < rounds; i++) {
+        const uint64_t line = mix64(seed ^ (grp * 0x9E3779B97F4A7C15ull + (uint64_t)i)) % nlines;
+        const uint4 v = buf[line * (uint64_t)lanes_per_line + (uint64_t)sub];
+        acc += v.x ^ v.y ^ v.z ^ v.w;
+    }
+    sink[t] = acc;
+}
+
+extern "C" int snap_debug_gather_lines(const void *buf, uint64_t bytes, int32_t line_bytes, int32_t rounds,
+                                       uint64_t threads, uint64_t seed, void *sink, void *stream) {
+    if (!buf || !sink || (line_bytes != 32 && line_bytes != 64 && line_bytes != 128) || rounds < 1 || threads == 0 ||
+        bytes < (uint64_t)line_bytes || (threads % 256) != 0 || ((uintptr_t)buf & 127) != 0)
+        return SNAP_EINVAL;
+    const int lpl = line_bytes / 16;
+    if (threads % (uint64_t)lpl != 0) return SNAP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t nlines = bytes / (uint64_t)line_bytes;
+    timed("gather_lines", st, [&] {
+        hipLaunchKernelGGL(k_gather_lines, dim3((unsigned)(threads / 256)), dim3(256), 0, st, (const uint4 *)buf, nlines,
+                           lpl, rounds, seed, (uint32_t *)sink);
+    });
+    return hipGetLastError() == hipSuccess ? SNAP_OK : SNAP_EDEVICE;
+}
+
 extern "C" int snap_debug_copy(const void *src, void *dst, uint64_t bytes, void *stream) {
     if (!src || !dst || (bytes & 3)) return SNAP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
