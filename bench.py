@@ -374,7 +374,7 @@ def read_traffic(path, kernel, workload, schedule):
         sched = tuple(int(x) for x in kv.get("schedule", "").split(",") if x.strip())
         # the chunk-worker count changes which launches overlap, not what one launch reads
         # and writes (the counters are taken with every dispatch alone)
-        strip = lambda t: make_tuning(t).astuple()[:7]
+        strip = lambda t: make_tuning(t).astuple()[:7] + make_tuning(t).astuple()[8:]
         same = strip(sched) == strip(tuple(schedule))
         fresh = kv.get("source_sha1") == kernel_source_sha1()
         if kv.get("kernel") == kernel and kv.get("workload") == workload and same and fresh:

@@ -53,6 +53,8 @@ constexpr int VERIFY_KMAX = 1023;   // largest limit d_max(L) + c - 1
 constexpr int VERIFY_LMAX = 16384;  // longest read
 constexpr int LANE_KMAX = 63;       // lane-per-location verify: limit and read length bounds
 constexpr int LANE_LMAX = 512;
+constexpr int REQUEST_TOP_DEFAULT = 4;   // locations a single-location request takes (snap_tuning.request_top)
+constexpr int REQUEST_TOP_MAX = 16;
 // Verification requests live in one int16 per location: the limit, tagged for the
 // wave tile when the read is verified a wave per location; -1 = none.
 constexpr int REQ_WAVE = 0x4000;
@@ -1377,6 +1379,7 @@ struct ReplayArgs {
     const int64_t *rlist_n;
     int32_t round;              // 0 for the first replay of the chunk, then 1, 2, ...
     int32_t exact_rounds;       // short reads ask for single locations in rounds below this
+    int32_t request_top;        // a single-location request takes the this many best undecided locations
     int32_t lane_lmax;          // reads up to this length (limit <= 63) are verified one lane per location
     int64_t *pos;
     int8_t *strand;
@@ -1653,10 +1656,19 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                     if (res == -2) {
                         unresolved = true;
                         need_k = kb;
-                        if (lane_class && (all_undecided || lim < Kfull))
+                        if (lane_class && (all_undecided || lim < Kfull)) {
                             light_request(a, base, r, have && !scored && dc > vl && vl < lim, lim, false, lane);
-                        else
-                            light_request(a, base, r, lane == kb, lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
+                        } else {
+                            // the request_top best locations undecided at this limit
+                            bool pick = lane == kb;
+                            const bool open = have && !scored && dc > vl && vl < lim && m != 0;
+                            for (int q = 1; q < a.request_top; q++) {
+                                const int k2 = wave_argmax6((open && !pick) ? (uint32_t)__builtin_popcount(m) : 0u);
+                                if (k2 < 0) break;
+                                pick |= lane == k2;
+                            }
+                            light_request(a, base, r, pick, lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
+                        }
                         break;
                     }
                     if (lane == kb) scored = true;
@@ -1764,8 +1776,38 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                             return !scored_at(k) && dck > vlk && vlk < lim;
                         }, lim, false, lane);
                     } else {
-                        heavy_request(a, base, C, r, [&](int64_t k) { return k == kb; },
-                                      lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
+                        // the request_top best locations undecided at this limit, in
+                        // selection order (the next calls of this loop are likely among them)
+                        int64_t pick[REQUEST_TOP_MAX];
+                        int np = 0;
+                        pick[np++] = kb;
+                        for (int m = 1; m < a.request_top; m++) {
+                            uint32_t bv = 0, bk = 0xFFFFFFFFu;
+                            for (int64_t k = lane; k < C; k += 64) {
+                                if (scored_at(k)) continue;
+                                bool taken = false;
+                                for (int q = 0; q < np; q++) taken |= pick[q] == k;
+                                if (taken || ed_answer(dc_at(k), vl_at(k), lim) != -2) continue;
+                                const uint32_t v = (uint32_t)__builtin_popcount(mask_at(k) & prefix);
+                                if (v > bv) { bv = v; bk = (uint32_t)k; }
+                            }
+                            uint64_t alive2 = __ballot(bv != 0);
+                            if (!alive2) break;
+                            for (int b = 5; b >= 0; b--) {
+                                const uint64_t hb = alive2 & __ballot((bv >> b) & 1u);
+                                if (hb) alive2 = hb;
+                            }
+                            for (int b = 31 - __builtin_clz((uint32_t)C); b >= 0; b--) {
+                                const uint64_t hb = alive2 & __ballot(((bk >> b) & 1u) == 0);
+                                if (hb) alive2 = hb;
+                            }
+                            pick[np++] = (int64_t)(uint32_t)lane_i32((int)bk, __builtin_ctzll(alive2));
+                        }
+                        heavy_request(a, base, C, r, [&](int64_t k) {
+                            bool w = false;
+                            for (int q = 0; q < np; q++) w |= pick[q] == k;
+                            return w;
+                        }, lane_class ? lim : (REQ_WAVE | lim), !lane_class, lane);
                     }
                     break;
                 }
@@ -1998,13 +2040,30 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                 const int code = lane_class ? req_lim : (REQ_WAVE | req_lim);
                 const int lr = req_lim;
                 uint32_t n = 0, wbits = 0;
+                if (req_kind == 0) {
+                    // the request_top best locations undecided at this limit, in selection
+                    // order: votes over the seeds so far descending, then index
+                    wbits = 1u << need_k;
+                    for (int q = 1; q < a.request_top; q++) {
+                        int kb2 = -1, bv2 = 0;
+#pragma unroll
+                        for (int k = 0; k < TINY_LOCS; k++) {
+                            const int dc = (int)(DV[k] & 0xFFFFu), vl = (int)(int16_t)(DV[k] >> 16);
+                            const bool open = k < C && !((scored >> k) & 1u) && !((wbits >> k) & 1u) && dc > vl &&
+                                              vl < lr;
+                            const int v = open ? __builtin_popcount(M[k] & prefix) : 0;
+                            if (v > bv2) { bv2 = v; kb2 = k; }
+                        }
+                        if (kb2 < 0) break;
+                        wbits |= 1u << kb2;
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < TINY_LOCS; k++) {
                     const int dc = (int)(DV[k] & 0xFFFFu), vl = (int)(int16_t)(DV[k] >> 16);
-                    bool want;
-                    if (req_kind == 0) want = k == need_k;
-                    else if (req_kind == 1) want = !((scored >> k) & 1u) && dc > vl && vl < lr;
-                    else want = !((scored >> k) & 1u) && (M[k] & prefix) && dc > vl && vl < lr;
+                    bool want = false;
+                    if (req_kind == 1) want = !((scored >> k) & 1u) && dc > vl && vl < lr;
+                    else if (req_kind == 2) want = !((scored >> k) & 1u) && (M[k] & prefix) && dc > vl && vl < lr;
                     if (k < C && want) wbits |= 1u << k;
                 }
 #pragma unroll
@@ -2264,8 +2323,9 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {5, 6, 6, 0, 1, 0, 0, 0};   // stage-1 seeds and first limit, final first limit, lane-tile read bound,
-                                        // exact-request rounds, first-verification seeds
+snap_tuning g_tune = {5, 6, 6, 0, 1, 0, 0, 0, 0};   // stage-1 seeds and first limit, final first limit, lane-tile
+                                           // read bound, exact-request rounds, first-verification seeds, ...
+
 
 constexpr int KCAP_NONE = 1 << 20;
 constexpr int MAX_WORKERS = 4;   // chunk workers of one call (host thread + stream each)
@@ -2319,7 +2379,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0 || t->chunk_reads < 0 || t->workers < 0) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0 || t->chunk_reads < 0 || t->workers < 0 || t->request_top < 0 || t->request_top > REQUEST_TOP_MAX) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -2372,7 +2432,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
-    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0 || tune.chunk_reads < 0 || tune.workers < 0) return SNAP_EINVAL;
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0 || tune.chunk_reads < 0 || tune.workers < 0 || tune.request_top < 0 || tune.request_top > REQUEST_TOP_MAX) return SNAP_EINVAL;
+    const int request_top = tune.request_top > 0 ? tune.request_top : REQUEST_TOP_DEFAULT;
     const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
     const int exact_rounds = tune.exact_rounds;
     const int verify_seeds = tune.verify_seeds;
@@ -2776,7 +2837,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 }
             }
             ReplayArgs ra{probe, key_c, mask_c, dcap, vlim, coff, ccount, bmin, scored, lengths, ps, rule, sh,
-                          alias, rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, lane_lmax,
+                          alias, rflag, rq, short_list, reqcount, nullptr, nullptr, 0, exact_rounds, request_top,
+                          lane_lmax,
                           pos, strand, dist, second, call};
             const unsigned rb = (unsigned)std::min<int64_t>((nr + 3) / 4, 8192);
             // reads with up to TINY_LOCS locations replay a lane each; the others, a wave
@@ -2827,7 +2889,9 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     const int kfull = std::min(Kmax, LANE_KMAX);
                     const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
                     // requested limits up to 11 keep their rows in registers too
-                    const int kmf = kfull <= 7 ? 7 : (kfull <= 11 ? 11 : (kfull <= 15 ? 15 : (kfull <= 31 ? 31 : 63)));
+                    // (17: limits of d_max 15-16 reads without the LDS rows of 31)
+                    const int kmf = kfull <= 7 ? 7 : (kfull <= 11 ? 11 : (kfull <= 15 ? 15 : (kfull <= 17 ? 17 :
+                                    (kfull <= 31 ? 31 : 63))));
                     const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 11 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
                     VerifyArgs vq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
                                   coff + nr, rule, RW, TWf, dcap, vlim, steps, long_list, req_off + nrep, rq};
@@ -2842,6 +2906,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                             hipLaunchKernelGGL(k_verify_requested<11>, dim3(vb), dim3(64), ldsf, st, vq);
                         else if (kmf == 15)
                             hipLaunchKernelGGL(k_verify_requested<15>, dim3(vb), dim3(64), ldsf, st, vq);
+                        else if (kmf == 17)
+                            hipLaunchKernelGGL(k_verify_requested<17>, dim3(vb), dim3(64), ldsf, st, vq);
                         else if (kmf == 31)
                             hipLaunchKernelGGL(k_verify_requested<31>, dim3(vb), dim3(64), ldsf, st, vq);
                         else

@@ -178,6 +178,21 @@ def test_pass_schedule_invariance(snapgpu, oracle_mod, synth_mod, seeds, limit, 
         snapgpu.set_tuning(*old)
 
 
+@pytest.mark.parametrize("top", [1, 2, 8, 16])
+def test_request_top_invariance(snapgpu, oracle_mod, synth_mod, top):
+    """How many best-voted undecided locations a single-location request takes changes the
+    verification rounds, never the outputs: 100 and 250 bp reads at d_max 15 (reads with
+    more than 64 locations in the repeats), exact requests for up to 5 rounds."""
+    from synth.workloads import HUMAN
+    w, g, reads = _world(synth_mod, HUMAN, 2_000_000, 8_000)
+    old = snapgpu.get_tuning()
+    try:
+        snapgpu.set_tuning(5, 6, 6, 0, 5, 0, 0, 0, top)
+        _check(snapgpu, oracle_mod, w, g, reads, f"request_top {top}")
+    finally:
+        snapgpu.set_tuning(*old)
+
+
 def test_batch_composition_invariance(snapgpu, synth_mod):
     """A read's output does not depend on the other reads in the batch or their order."""
     from synth.workloads import MID
