@@ -35,6 +35,7 @@ GATHER_BYTES_PER_HIT = 4 + 8          # position read, hit record written
 DEDUPE_BYTES_PER_HIT = 8              # hit record read
 DEDUPE_BYTES_PER_LOC = 12             # location key + seed mask written
 VERIFY_OPS_PER_STEP = 30              # integer ops per diagonal extension (neighbour max, bounds, one 16-base compare)
+SELECT_OPS_PER_VISIT = 4              # integer ops per location looked at by a selection (and + popcount, compare + select)
 
 
 def log(*a):
@@ -325,9 +326,28 @@ def roofline_of(kern, ctr, prefer=None, method=None):
         else:
             work = executed
             extra["work"] = "diagonal extensions the kernel ran (no oracle sample in this run)"
+    elif dom.startswith("replay"):
+        # Algorithm 1's control: each selection of "the unscored location with the most seeds
+        # hitting" looks at every candidate location (the oracle's count on the sample),
+        # shared among the replay kernels in proportion to their time
+        bound, unit, peak = "alu", "TOP/s", VALU_PEAK_TOPS
+        rep = [k for k in kern if k.startswith("replay")]
+        rt = sum(kern[k][1] for k in rep)
+        if method and "select_visits_per_read" in method:
+            work = (method["select_visits_per_read"] * ctr["reads"] * (total_ms / rt if rt > 0 else 1.0)
+                    * SELECT_OPS_PER_VISIT * per_launch / 1e12)
+            extra = {"work": "Algorithm 1's own selection scans (oracle sample) x 4 ops per location looked at",
+                     "ops_per_visit": SELECT_OPS_PER_VISIT,
+                     "select_visits_per_read_method": method["select_visits_per_read"]}
+        else:
+            work = None
+            extra = {"work": "no oracle sample in this run"}
     else:
         bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
-        work = float("nan")
+        work = None
+    if work is None:
+        return {"bound": bound, "kernel": dom, "achieved": None, "peak": peak, "unit": unit, "frac": None,
+                "avg_launch_ms": round(total_ms / launches, 4), "launches": launches, **extra}
     achieved = work / avg_s
     return {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 5), "avg_launch_ms": round(total_ms / launches, 4), "launches": launches,
@@ -439,6 +459,7 @@ def oracle_check(g, reads, w, got, seconds, single_seconds=4.0, probe=4000, prob
     method = {"reads": len(idx), "ed_calls_per_read": round(st["ed_calls"] / len(idx), 3),
               "lv_extensions_per_read": round(st["lv_extensions"] / len(idx), 2),
               "seeds_looked_up_per_read": round(st["seeds_looked_up"] / len(idx), 3),
+              "select_visits_per_read": round(st["select_visits"] / len(idx), 2),
               "candidates_per_read": round(st["candidates"] / len(idx), 2)}
     # the oracle hands out ranges of at least 4096 reads (Section 2.3's rule), so a small
     # sample keeps fewer threads busy than it was given

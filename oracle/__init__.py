@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("seeds_looked_up", "seeds_over_limit", "seeds_with_n", "candidates", "ed_calls", "ed_over_limit",
-                 "lv_extensions", "index_lookups")]
+                 "lv_extensions", "index_lookups", "select_visits")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -622,12 +622,18 @@ static void align_one(const orc_index *ix, work *w, const uint8_t *read, int32_t
             if (e == 0 || cmp_vkey(&w->v[e], &w->v[e - 1]) != 0) vote(w, w->v[e].p, w->v[e].strand);
         if (o % s == 0 && np == stride) t++;
         int64_t k = select_unscored(w);
+        stt->select_visits += w->nc;
         if (k >= 0) score(ix, w, &st, k, L, dmax, pr, stt, lg);
         if (st.d_best < c && st.d_second < st.d_best + c) {
             call = 2;   /* multiple hits: no better hit could be confident */
         } else if (st.d_best < ORC_INF && t >= st.d_best + c) {
             /* any location not yet found is at least t edits away */
-            while ((k = select_unscored(w)) >= 0) score(ix, w, &st, k, L, dmax, pr, stt, lg);
+            for (;;) {
+                k = select_unscored(w);
+                stt->select_visits += w->nc;
+                if (k < 0) break;
+                score(ix, w, &st, k, L, dmax, pr, stt, lg);
+            }
             break;
         }
     }
@@ -742,6 +748,7 @@ static void *worker(void *arg) {
     jb->total.ed_over_limit += stt.ed_over_limit;
     jb->total.lv_extensions += stt.lv_extensions;
     jb->total.index_lookups += stt.index_lookups;
+    jb->total.select_visits += stt.select_visits;
     pthread_mutex_unlock(&jb->mu);
     work_free(&w);
     return NULL;

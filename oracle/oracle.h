@@ -42,6 +42,8 @@ typedef struct {
     int64_t lv_extensions;     /* sum over calls of (min(D, limit) + 1)^2: the diagonal extensions a
                                   furthest-reaching-diagonal evaluation runs at each call's own limit */
     int64_t index_lookups;     /* seeds looked up in the index (stride per seed slot with a strided index) */
+    int64_t select_visits;     /* statistic: sum over selections of "the unscored location with the most
+                                  seeds hitting" of the candidate locations looked at (the scan's length) */
 } orc_stats;
 
 /* Index: every N-free window of length s, as sorted (key, position) pairs. */

@@ -126,3 +126,15 @@ def test_accuracy_grid_dmax(bench):
     assert bench.grid_dmax(1000, 0.05) == 75
     assert bench.grid_dmax(10000, 0.10) == 1022
     assert [row[1] for row in bench.ACCURACY_GRID].count(10000) == 3
+
+
+def test_roofline_of_a_replay_kernel(bench):
+    # the replays share Algorithm 1's selection scans by time: 3 of 4 ms to the heavy one
+    kern = {"replay_heavy": (10, 30.0), "replay": (10, 10.0), "verify": (10, 5.0)}
+    ctr = {"lv_steps": 1, "lv_steps_first": 1, "seed_slots": 0, "hits": 0, "locations": 0, "reads": 1_000_000}
+    r = bench.roofline_of(kern, ctr, None, {"select_visits_per_read": 50.0, "lv_extensions_per_read": 1.0})
+    assert r["kernel"] == "replay_heavy" and r["bound"] == "alu"
+    assert r["achieved"] == pytest.approx(50.0 * 1e6 * 0.75 * 4 / 10 / 3e-3 / 1e12, rel=1e-4)
+    # without an oracle sample there is no work figure, and nothing is NaN
+    q = bench.roofline_of(kern, ctr)
+    assert q["achieved"] is None and q["frac"] is None

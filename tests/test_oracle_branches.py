@@ -93,6 +93,9 @@ def test_third_limit_rejects_a_location_at_d_best(oracle_mod, bg, R, strand):
     assert st["seeds_looked_up"] == 4 and st["ed_calls"] == 3
     # diagonal extensions at each call's own limit, (min(D, limit) + 1)^2: 9 + 16 + 4
     assert st["lv_extensions"] == 29
+    # the selection scans the three locations after each of the four seeds, and once more
+    # when the remaining phase finds nothing left: 5 x 3
+    assert st["select_visits"] == 15
 
 
 @pytest.mark.parametrize("strand", [0, 1])

@@ -39,9 +39,9 @@ MUTATIONS = [
     ("text window of L + limit bases",
      "int64_t want = (int64_t)L + (lim > 0 ? lim : 0);", "int64_t want = (int64_t)L + (lim > 0 ? lim - 1 : 0);"),
     ("no early return while scoring the remaining locations",
-     "while ((k = select_unscored(w)) >= 0) score(ix, w, &st, k, L, dmax, pr, stt, lg);",
-     "while ((k = select_unscored(w)) >= 0) { score(ix, w, &st, k, L, dmax, pr, stt, lg); "
-     "if (st.d_best < c && st.d_second < st.d_best + c) { call = 2; break; } }"),
+     "                score(ix, w, &st, k, L, dmax, pr, stt, lg);\n            }",
+     "                score(ix, w, &st, k, L, dmax, pr, stt, lg);\n"
+     "                if (st.d_best < c && st.d_second < st.d_best + c) { call = 2; break; }\n            }"),
 ]
 
 PIN_TESTS = ["tests/test_oracle_algorithm1.py", "tests/test_oracle_branches.py", "tests/test_oracle_pins.py",
