@@ -1827,13 +1827,18 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
             }
             if (st.d_best < DINF && t >= st.d_best + c) {
                 // score every remaining location; vote counts are frozen now (kept per
-                // location in LDS, 0 for a scored one)
-                if (in_lds) {
-                    for (int64_t k = lane; k < C; k += 64)
-                        Llev[k] = scored_at(k) ? 0 : (uint8_t)__builtin_popcount(mask_at(k) & prefix);
-                    __builtin_amdgcn_wave_barrier();
+                // location in LDS, 0 for a scored one). Only the vote levels some unscored
+                // location has are visited (a bit per level, OR-ed over the wave).
+                uint64_t levbits = 0;
+                for (int64_t k = lane; k < C; k += 64) {
+                    const int v = scored_at(k) ? 0 : __builtin_popcount(mask_at(k) & prefix);
+                    if (in_lds) Llev[k] = (uint8_t)v;
+                    levbits |= 1ull << v;
                 }
+                for (int m = 1; m < 64; m <<= 1) levbits |= shfl_xor64(levbits, m);
+                if (in_lds) __builtin_amdgcn_wave_barrier();
                 for (int lev = __builtin_popcount(prefix); lev >= 1 && !unresolved; lev--) {
+                    if (!((levbits >> lev) & 1u)) continue;
                     for (int64_t c0 = 0; c0 < C && !unresolved; c0 += 64) {
                         const int64_t k = c0 + lane;
                         bool in = false;
