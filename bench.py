@@ -953,7 +953,13 @@ def bench_plain(args, w, dev):
 
     # roofline of the dominant kernel, with HBM traffic from the committed counter summary
     roofline = roofline_of(kern, ctr, method=method)
-    roofline["traffic"] = read_traffic(args.traffic, roofline["kernel"], w.name, snapgpu.get_tuning())
+    line_phases = phases_of(kern, ctr, method)
+    roofline["traffic"] = read_traffic(args.traffic.format(kernel=roofline["kernel"], workload=w.name),
+                                       roofline["kernel"], w.name, snapgpu.get_tuning())
+    for ph in line_phases.values():
+        if ph and "kernel" in ph:
+            ph["traffic"] = read_traffic(args.traffic.format(kernel=ph["kernel"], workload=w.name), ph["kernel"],
+                                         w.name, snapgpu.get_tuning())
 
     line = {
         "metric": "reads aligned/s", "value": round(reads_per_s, 1), "unit": "reads/s",
@@ -979,7 +985,7 @@ def bench_plain(args, w, dev):
         "schedule": tune_info,
         "roofline": roofline,
         # the two phases the method hinges on: gather (HBM-bound) and verify (VALU-bound)
-        "phases": phases_of(kern, ctr, method),
+        "phases": line_phases,
         "cpu_baseline": cpu,
         "method_work": method,
     }
@@ -997,8 +1003,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--requests", type=int, default=2000, help="served workload: requests per load level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "verify_traffic_mid.txt"),
-                    help="counter summary giving the dominant kernel's HBM bytes per launch")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "{kernel}_traffic_{workload}.txt"),
+                    help="counter summary giving a kernel's HBM bytes per launch ({kernel}, {workload} filled in)")
     ap.add_argument("--genome-len", type=int, default=0, help="override the genome length (batched/served runs)")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule")
     ap.add_argument("--host-index", action="store_true", help="build the index on the host (snap_index_build)")
