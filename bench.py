@@ -566,12 +566,13 @@ def bench_batched(args, w, dev):
         snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True, tuning=tuning)
     torch.cuda.synchronize()
     batched_s = (time.perf_counter() - t0) / args.steps
-    # one profiled step of its own: per-kernel times and counters
-    snapgpu.profile_begin()
-    snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True, tuning=tuning)
-    torch.cuda.synchronize()
-    kern = snapgpu.profile_end()
-    ctr = snapgpu.profile_counters()
+    # one profiled step of its own (one chunk worker): per-kernel times and counters
+    from paper_1111_5572_amd import make_tuning
+    t1 = make_tuning(tuning if tuning is not None else snapgpu.get_tuning()).astuple()
+    t1 = t1[:7] + (1,) + t1[8:]
+    kern, ctr, _ = profiled_steps(
+        lambda: snapgpu.align(gix, rb, ln, d_max, params, out=out, workspace=ws, max_len=ml, batched=True,
+                              tuning=t1), 1, dev)
     got = out.numpy()
     same = all(np.array_equal(np.asarray(a).astype(np.int64), np.asarray(b).astype(np.int64))
                for a, b in zip(got, plain_out))
@@ -765,6 +766,37 @@ def bench_served(args, w, dev):
     print(json.dumps(line), flush=True)
 
 
+def profiled_steps(step, n, dev):
+    """Run `step` n times with profiling on and one chunk worker (the process-wide
+    schedule's worker field set to 1; a step that passes its own schedule sets it there),
+    between two marker launches of the library's copy kernel; returns (per-kernel times,
+    counters, ms per step)."""
+    import torch
+    import paper_1111_5572_amd as snapgpu
+    old = snapgpu.get_tuning()
+    one = old[:7] + (1,) + old[8:]
+    snapgpu.set_tuning(*one)
+    mark = torch.zeros(64, dtype=torch.int32, device=dev)
+    mark2 = torch.empty_like(mark)
+    try:
+        torch.cuda.synchronize()
+        snapgpu.debug_copy(mark, mark2, 256)
+        torch.cuda.synchronize()
+        snapgpu.profile_begin()
+        tp = time.perf_counter()
+        for _ in range(n):
+            step()
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - tp) / n
+        kern = snapgpu.profile_end()
+        ctr = snapgpu.profile_counters()
+        snapgpu.debug_copy(mark, mark2, 256)
+        torch.cuda.synchronize()
+    finally:
+        snapgpu.set_tuning(*old)
+    return kern, ctr, ms
+
+
 def streamed_steps(gix, reads, w, params, got, chunks, steps, dev):
     """The batch aligned from pinned host memory: the reads go to the device in `chunks`
     parts (one stream copies part k+1 in while part k is aligned on another; two device
@@ -923,17 +955,13 @@ def bench_plain(args, w, dev):
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {reads_per_s:,.0f} reads/s")
 
     # profiled steps of their own: per-kernel times (an event pair on each launch's
-    # stream) and device counters
+    # stream) and device counters, with one chunk worker so that each kernel runs alone
+    # and its events time the kernel itself; a marker launch before and after (the
+    # library's copy kernel on 256 bytes) brackets these steps in a profiler's trace
     prof_steps = max(1, min(args.steps, 2))
-    snapgpu.profile_begin()
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    for _ in range(prof_steps):
-        snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, stream=stream, max_len=max_len)
-    torch.cuda.synchronize()
-    prof_ms = 1000.0 * (time.perf_counter() - tp) / prof_steps
-    kern = snapgpu.profile_end()
-    ctr = snapgpu.profile_counters()
+    kern, ctr, prof_ms = profiled_steps(
+        lambda: snapgpu.align(gix, rb, ln, w.params.d_max, params, out=out, workspace=ws, stream=stream,
+                              max_len=max_len), prof_steps, dev)
     log(f"profiled {prof_steps} steps: {prof_ms:.2f} ms/step")
     log("kernels: " + ", ".join(f"{k} {v[1] / max(v[0], 1):.3f} ms x{v[0]}" for k, v in kern.items()))
     log(f"counters: {ctr}")
@@ -980,6 +1008,7 @@ def bench_plain(args, w, dev):
         "dup_classes": dup,
         "calls": {"not_found": int(calls[0]), "single": int(calls[1]), "multiple": int(calls[2])},
         "profiled_ms_per_step": round(prof_ms, 3),
+        "profiled_workers": 1,
         "kernel_ms_per_step": {k: round(v[1] / prof_steps, 4) for k, v in kern.items()},
         "counters_per_step": {k: v // prof_steps for k, v in ctr.items()},
         "schedule": tune_info,
