@@ -997,7 +997,7 @@ __device__ __forceinline__ void verify_lane(const VerifyArgs &a, int64_t k, uint
 
     uint32_t nsteps = 1;
     int D;
-    if constexpr (KMAX <= 11)
+    if constexpr (KMAX <= 17)
         D = anyn ? lv_lane_reg<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane_reg<KMAX, false>(st, L, Tn, K, nsteps);
     else
         D = anyn ? lv_lane<KMAX, true>(st, L, Tn, K, nsteps) : lv_lane<KMAX, false>(st, L, Tn, K, nsteps);
@@ -2895,15 +2895,16 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                     hipLaunchKernelGGL(k_flatten_requests, dim3(fb), dim3(256), 0, st, qa, req_off, long_list);
                     const int kfull = std::min(Kmax, LANE_KMAX);
                     const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
-                    // requested limits up to 11 keep their rows in registers too
-                    // (17: limits of d_max 15-16 reads without the LDS rows of 31)
+                    // requested limits up to 17 keep their rows in registers too (17: the
+                    // limits of d_max 15-16 reads)
                     const int kmf = kfull <= 7 ? 7 : (kfull <= 11 ? 11 : (kfull <= 15 ? 15 : (kfull <= 17 ? 17 :
                                     (kfull <= 31 ? 31 : 63))));
-                    const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 11 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
+                    const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 17 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
                     VerifyArgs vq{ix->d.gcode, ix->d.gmask, ix->d.G, rcode, rmask, roff, lengths, ps, key_c, cread,
                                   coff + nr, rule, RW, TWf, dcap, vlim, steps, long_list, req_off + nrep, rq};
-                    // as many waves as fit the device (the count is on the device): rows in
-                    // registers leave room for 24 a CU, rows in LDS for 16
+                    // as many waves as fit the device (the count is on the device): rows of
+                    // limits up to 11 in registers leave room for 24 a CU (71 VGPRs), of 15 and
+                    // 17 for 16 (88-98 VGPRs), rows in LDS for 16
                     const int64_t per_cu = kmf <= 11 ? 24 : 16;
                     const unsigned vb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)cus * per_cu));
                     timed("verify_request", st, [&] {
