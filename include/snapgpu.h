@@ -241,8 +241,11 @@ int32_t snap_max_limit(void);
  * was verified with, that location is verified again with exactly the limit the
  * replay uses, or (reads in the lane tile, once the limit is below d_max(L) + c - 1
  * or after exact_rounds rounds) every unscored location still undecided at that
- * limit, and the read is replayed again. Only reads that need more seeds than the first pass probed go on to the
- * final pass. 0 in a field means "no cap" (no first pass when pass1_seeds and
+ * limit, and the read is replayed again. For reads in the lane tile (plain calls, no
+ * duplicate classes, verify_seeds 0) the location Algorithm 1 scores first is verified
+ * at the read's full limit before the others, and when its distance d1 is within
+ * d_max(L) the others are verified with min(limit, d1 + c - 1). Only reads that need
+ * more seeds than the first pass probed go on to the final pass. 0 in a field means "no cap" (no first pass when pass1_seeds and
  * pass1_limit are both 0). Outputs never depend on these values.
  */
 typedef struct {

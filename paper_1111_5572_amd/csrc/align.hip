@@ -745,10 +745,16 @@ __global__ __launch_bounds__(NT) void k_dedupe_heavy(DedupeArgs a, uint64_t *gsc
 // arrays; the lanes take 64 of them at a time, each finding its read by a binary
 // search over the reads' first location slots in LDS, and copy location o of read r
 // from slot hoff[r] + (o - coff[r]).
+// With `lead` set, each read's lead location is recorded too: the location of Algorithm 1's
+// first EditDistance call. That call comes after the first seed slot that has a hit, when
+// each of that slot's locations has one vote, so it takes the smallest (p, strand) among
+// them: the first location in key order whose lowest seed bit is the lowest of the read.
+constexpr uint32_t LEAD_NONE = 0xFFFFFFFFu;
 __global__ __launch_bounds__(256) void k_compact(const int64_t *hoff, const int64_t *coff, int64_t nr,
                                                  const uint64_t *key_in, const uint32_t *mask_in, uint64_t *key_out,
-                                                 uint32_t *mask_out, uint32_t *cread) {
+                                                 uint32_t *mask_out, uint32_t *cread, uint32_t *lead) {
     __shared__ int64_t s_src[4][64], s_dst[4][64];
+    __shared__ unsigned long long s_lead[4][64];   // (lowest seed bit << 40) | location, minimum per read
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -758,6 +764,7 @@ __global__ __launch_bounds__(256) void k_compact(const int64_t *hoff, const int6
         if (lane < nrd) {
             s_src[wv][lane] = hoff[r0 + lane];
             s_dst[wv][lane] = coff[r0 + lane];
+            s_lead[wv][lane] = ~0ull;
         }
         const int64_t d0 = coff[r0];
         __builtin_amdgcn_wave_barrier();
@@ -771,10 +778,20 @@ __global__ __launch_bounds__(256) void k_compact(const int64_t *hoff, const int6
                     if (s_dst[wv][mid] <= o) lo = mid; else hi = mid - 1;
                 }
                 const int64_t src = s_src[wv][lo] + (o - s_dst[wv][lo]);
+                const uint32_t m = mask_in[src];
                 key_out[o] = key_in[src];
-                mask_out[o] = mask_in[src];
+                mask_out[o] = m;
                 cread[o] = (uint32_t)(r0 + lo);
+                if (lead) {
+                    const unsigned long long bit = m ? (unsigned long long)__builtin_ctz(m) : 63ull;
+                    atomicMin(&s_lead[wv][lo], (bit << 40) | (unsigned long long)o);
+                }
             }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lead && lane < nrd) {
+            const unsigned long long v = s_lead[wv][lane];
+            lead[r0 + lane] = v == ~0ull ? LEAD_NONE : (uint32_t)(v & ((1ull << 40) - 1));
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -800,6 +817,8 @@ struct VerifyArgs {
     const uint32_t *list;       // locations routed to this kernel (null: all)
     const int64_t *nlist_ptr;   // their number when list is set
     int16_t *rq;                // requested limit per location (null: the read's limit); cleared once verified
+    const uint32_t *lead = nullptr;   // per read (chunk index): its lead location, verified on its own
+    const int16_t *rlim = nullptr;    // per read: a further cap on the limit (with lead)
 };
 
 // Per-lane LDS arrays are laid out [word][lane], so a wave's accesses to its
@@ -945,9 +964,12 @@ __device__ __forceinline__ void verify_lane(const VerifyArgs &a, int64_t k, uint
     const uint64_t key = a.key[k];
     const int64_t p = (int64_t)(key >> 1);
     const int strand = (int)(key & 1);
-    const int64_t g = gid(a.ps, a.cread[k]);
+    const uint32_t cr = a.cread[k];
+    if (a.lead && a.lead[cr] == (uint32_t)k) return;   // verified at the full limit already
+    const int64_t g = gid(a.ps, cr);
     const int L = a.len[g];
-    const int K = a.rq ? (int)a.rq[k] : min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
+    int K = a.rq ? (int)a.rq[k] : min(dmax_for_length(a.rule, L) + a.rule.c - 1, a.ps.Kcap);
+    if (a.rlim) K = min(K, (int)a.rlim[cr]);
     const int64_t xb = STREAM_GUARD + a.roff[g];
     const int Tn = (int)min((int64_t)a.G - p, (int64_t)L + K);
 
@@ -1027,6 +1049,28 @@ template <int KMAX>
 __global__ __launch_bounds__(64) void k_verify_requested(VerifyArgs a) {
     extern __shared__ uint32_t sm[];
     verify_lanes<KMAX>(a, sm);
+}
+
+// Lane per read: its lead location (Algorithm 1's first call) at the read's full limit
+// (a.ps.Kcap set above every limit), then the cap on its other locations' limits for the
+// first verification. After a first call at distance d1 <= d_max(L), every later call of
+// the replay runs at limit d1 + c - 1 or below (the best distance only falls, and a
+// second location within c lowers the limit to d_best - 1), so verifying the others at
+// min(Kpass, d1 + c - 1) answers as many calls as verifying them at Kpass does.
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_verify_lead(VerifyArgs a, const uint32_t *lead, int16_t *rlim, int Kpass) {
+    extern __shared__ uint32_t sm[];
+    for (int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x; r < a.ps.nr; r += (int64_t)gridDim.x * 64) {
+        const uint32_t k = lead[r];
+        int lim = Kpass;
+        if (k != LEAD_NONE) {
+            verify_lane<KMAX>(a, (int64_t)k, sm);
+            const int d1 = (int)a.dcap[k];
+            const int dm = dmax_for_length(a.rule, a.len[gid(a.ps, r)]);
+            if (d1 <= dm) lim = min(Kpass, d1 + a.rule.c - 1);
+        }
+        rlim[r] = (int16_t)lim;
+    }
 }
 
 // Locations whose read or limit is too large for one lane: one wave per location.
@@ -2280,6 +2324,9 @@ Layout make_layout(int64_t n, int64_t B, int NS, int hmax, int64_t R, int64_t po
     // read flags; replay and next-pass lists, request counts, light-replay list; request offsets
     l.off_req = o; o = align256(o + (size_t)R); o = align256(o + 4 * sizeof(uint32_t) * (size_t)R);
     o = align256(o + sizeof(int64_t) * (size_t)(R + 1));
+    // lead location and first-verification limit per read
+    o = align256(o + sizeof(uint32_t) * (size_t)R);
+    o = align256(o + sizeof(int16_t) * (size_t)R);
     const int64_t minslots = (int64_t)NS * hmax;
     if (pool_slots < minslots) pool_slots = minslots;
     l.pool_slots = pool_slots;
@@ -2554,6 +2601,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         uint32_t *short_list, *long_list;
         int16_t *rq;
         uint32_t *alias;
+        uint32_t *lead;
+        int16_t *rlim;
     };
     Worker wk[MAX_WORKERS];
     for (int w = 0; w < workers; w++) {
@@ -2573,6 +2622,8 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         W.reqcount = W.pend_local + R;
         W.light_list = W.reqcount + R;
         W.req_off = (int64_t *)(cb + align256(l.off_req + (size_t)R) + align256(4 * sizeof(uint32_t) * (size_t)R));
+        W.lead = (uint32_t *)((char *)W.req_off + align256(sizeof(int64_t) * (size_t)(R + 1)));
+        W.rlim = (int16_t *)((char *)W.lead + align256(sizeof(uint32_t) * (size_t)R));
         char *pool = cb + l.off_pool;
         auto carve = [&](size_t bytes) { char *q = pool; pool += align256(bytes); return (void *)q; };
         W.hk = (uint64_t *)carve(8 * (size_t)PS);
@@ -2673,6 +2724,11 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         int16_t *rq = W.rq;
         // representatives of exact-duplicate classes, when the index has classes
         uint32_t *alias = (ix->d.rep != nullptr && ix->d.dup_w > 0) ? W.alias : nullptr;
+        // lead verification: each read's first call at its full limit, then the first
+        // verification of its other locations at the limit that call leaves
+        const bool lead_mode = all_lane && !batched && !alias && !(verify_seeds > 0 && verify_seeds < NSp);
+        uint32_t *lead = W.lead;
+        int16_t *rlim = W.rlim;
         unsigned long long *nalias = (unsigned long long *)(misc + 12);
         unsigned long long *steps_sum = (unsigned long long *)(misc + 6);
         unsigned long long *steps_first = (unsigned long long *)(misc + 7);
@@ -2766,7 +2822,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
             if (total > 0) {
                 const unsigned cb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + 255) / 256, 8192));
                 timed("compact", st, [&] { hipLaunchKernelGGL(k_compact, dim3(cb), dim3(256), 0, st, hoff, coff, nr,
-                                   key_res, mask_res, key_c, mask_c, cread); });
+                                   key_res, mask_res, key_c, mask_c, cread, lead_mode ? lead : nullptr); });
             }
             if (total > 0) {
                 const int64_t *ncand = coff + nr;
@@ -2824,6 +2880,37 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                         HIP_OK(select_idx(sel_tmp, sel_tb, total, FirstSeedsPred{mask_c, ncand, bits, alias}, short_list, sel_n + 5, st));
                         va.list = short_list;
                         va.nlist_ptr = sel_n + 5;
+                    }
+                    if (lead_mode) {
+                        // the lead locations at the full limit, a lane per read (the lane tile
+                        // of the requested verification), and each read's cap for the others
+                        const int kfull = std::min(Kmax, LANE_KMAX);
+                        const int TWf = (std::max(lane_L, 1) + kfull + 15) / 16 + 1;
+                        const int kmf = kfull <= 7 ? 7 : (kfull <= 11 ? 11 : (kfull <= 15 ? 15 : (kfull <= 17 ? 17 :
+                                        (kfull <= 31 ? 31 : 63))));
+                        const size_t ldsf = (size_t)64 * 4 * (RW + TWf) + (kmf > 17 ? (size_t)64 * 2 * (2 * kmf + 3) : 0);
+                        VerifyArgs vl = va;
+                        vl.ps.Kcap = 1 << 14;
+                        vl.TW = TWf;
+                        vl.list = nullptr;
+                        vl.rq = nullptr;
+                        const unsigned lb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nr + 63) / 64, (int64_t)cus * 16));
+                        timed("verify_lead", st, [&] {
+                            if (kmf == 7)
+                                hipLaunchKernelGGL(k_verify_lead<7>, dim3(lb), dim3(64), ldsf, st, vl, lead, rlim, Kp);
+                            else if (kmf == 11)
+                                hipLaunchKernelGGL(k_verify_lead<11>, dim3(lb), dim3(64), ldsf, st, vl, lead, rlim, Kp);
+                            else if (kmf == 15)
+                                hipLaunchKernelGGL(k_verify_lead<15>, dim3(lb), dim3(64), ldsf, st, vl, lead, rlim, Kp);
+                            else if (kmf == 17)
+                                hipLaunchKernelGGL(k_verify_lead<17>, dim3(lb), dim3(64), ldsf, st, vl, lead, rlim, Kp);
+                            else if (kmf == 31)
+                                hipLaunchKernelGGL(k_verify_lead<31>, dim3(lb), dim3(64), ldsf, st, vl, lead, rlim, Kp);
+                            else
+                                hipLaunchKernelGGL(k_verify_lead<63>, dim3(lb), dim3(64), ldsf, st, vl, lead, rlim, Kp);
+                        });
+                        va.lead = lead;
+                        va.rlim = rlim;
                     }
                     timed("verify", st, [&] {
                         if (kmax_t == 7)
