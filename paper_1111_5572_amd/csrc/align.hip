@@ -63,9 +63,9 @@ constexpr uint32_t REQ_WAVE_READ = 0x80000000u;
 // Replay of reads with more than 64 locations: a wave stages up to HEAVY_LDS_LOCS of
 // them in LDS (seed mask, capped distance | verified limit << 16, scored bit, and
 // for the phase that scores every remaining location the vote count); a read with
-// more works in global memory. 512 keeps the LDS of a 4-wave workgroup at 18.7 KB, so
-// 32 waves fit a CU (1024: 37.4 KB, 16 waves; measured 104.2 against 102.9 M reads/s
-// at human scale).
+// more works in global memory. 512 keeps the LDS of a 4-wave workgroup at 18.7 KB
+// (1024: 37.4 KB); the kernel's registers hold it at 12 waves a CU either way (measured
+// 104.2 against 102.9 M reads/s at human scale with 512).
 constexpr int HEAVY_LDS_LOCS = 512;
 __host__ __device__ constexpr int heavy_lds_words(int cap) { return 2 * cap + cap / 32 + cap / 4; }
 // Outcome of a read's replay in a pass.
