@@ -263,10 +263,12 @@ typedef struct {
     int32_t workers;        /* a batch of several chunks is worked by up to this many host threads
                                with a stream each (0 = 2, at most 4), as many as the workspace holds
                                chunk parts for */
-    int32_t request_top;    /* a replay that asks for one location at the limit it needs asks, in the
-                               same round, for this many of the best-voted locations undecided at that
-                               limit (the calls that likely follow): fewer replay rounds for more
-                               verification (0 = 4, at most 16) */
+    int32_t request_top;    /* a replay of a lane-tile read that asks for one location at the limit
+                               it needs asks, in the same round, for this many of the best-voted
+                               locations undecided at that limit (the calls that likely follow): fewer
+                               replay rounds for more verification (0 = 4, at most 16); reads in the
+                               wave tile, whose verifications at limits of hundreds are costly, ask
+                               for the one location */
 } snap_tuning;
 
 /* Set the process-wide schedule that snap_align (and snap_align_batched with a NULL

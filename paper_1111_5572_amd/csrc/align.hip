@@ -1425,7 +1425,7 @@ struct ReplayArgs {
     const int64_t *rlist_n;
     int32_t round;              // 0 for the first replay of the chunk, then 1, 2, ...
     int32_t exact_rounds;       // short reads ask for single locations in rounds below this
-    int32_t request_top;        // a single-location request takes the this many best undecided locations
+    int32_t request_top;        // a single-location request of a lane-tile read takes this many best undecided locations
     int32_t lane_lmax;          // reads up to this length (limit <= 63) are verified one lane per location
     int64_t *pos;
     int8_t *strand;
@@ -1705,10 +1705,12 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                         if (lane_class && (all_undecided || lim < Kfull)) {
                             light_request(a, base, r, have && !scored && dc > vl && vl < lim, lim, false, lane);
                         } else {
-                            // the request_top best locations undecided at this limit
+                            // the request_top best locations undecided at this limit (one for a
+                            // read of the wave tile: its verifications are costly)
                             bool pick = lane == kb;
                             const bool open = have && !scored && dc > vl && vl < lim && m != 0;
-                            for (int q = 1; q < a.request_top; q++) {
+                            const int top = lane_class ? a.request_top : 1;
+                            for (int q = 1; q < top; q++) {
                                 const int k2 = wave_argmax6((open && !pick) ? (uint32_t)__builtin_popcount(m) : 0u);
                                 if (k2 < 0) break;
                                 pick |= lane == k2;
@@ -1823,11 +1825,13 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
                         }, lim, false, lane);
                     } else {
                         // the request_top best locations undecided at this limit, in
-                        // selection order (the next calls of this loop are likely among them)
+                        // selection order (the next calls of this loop are likely among them;
+                        // one for a read of the wave tile, whose verifications are costly)
                         int64_t pick[REQUEST_TOP_MAX];
                         int np = 0;
                         pick[np++] = kb;
-                        for (int m = 1; m < a.request_top; m++) {
+                        const int top = lane_class ? a.request_top : 1;
+                        for (int m = 1; m < top; m++) {
                             uint32_t bv = 0, bk = 0xFFFFFFFFu;
                             for (int64_t k = lane; k < C; k += 64) {
                                 if (scored_at(k)) continue;
@@ -2093,9 +2097,11 @@ __global__ __launch_bounds__(256) void k_replay_tiny(ReplayArgs a) {
                 uint32_t n = 0, wbits = 0;
                 if (req_kind == 0) {
                     // the request_top best locations undecided at this limit, in selection
-                    // order: votes over the seeds so far descending, then index
+                    // order: votes over the seeds so far descending, then index (one for a
+                    // read of the wave tile)
                     wbits = 1u << need_k;
-                    for (int q = 1; q < a.request_top; q++) {
+                    const int top = lane_class ? a.request_top : 1;
+                    for (int q = 1; q < top; q++) {
                         int kb2 = -1, bv2 = 0;
 #pragma unroll
                         for (int k = 0; k < TINY_LOCS; k++) {
