@@ -269,6 +269,11 @@ typedef struct {
                                replay rounds for more verification (0 = 4, at most 16); reads in the
                                wave tile, whose verifications at limits of hundreds are costly, ask
                                for the one location */
+    int32_t pass1_max_len;  /* snap_align with a first pass: reads longer than this take every seed
+                               slot at once, in a complete pass over their own list with the first
+                               pass's limit, instead of the first and the final pass (a long read
+                               needs more round-0 seeds than pass1_seeds before Algorithm 1 can stop,
+                               d_best growing with the length); 0 = no such reads */
 } snap_tuning;
 
 /* Set the process-wide schedule that snap_align (and snap_align_batched with a NULL

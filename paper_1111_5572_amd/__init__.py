@@ -47,7 +47,7 @@ class KernelTime(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("pass1_seeds", "pass1_limit", "final_limit", "lane_max_len",
                                                "exact_rounds", "verify_seeds", "chunk_reads", "workers",
-                                               "request_top")]
+                                               "request_top", "pass1_max_len")]
 
     def astuple(self):
         return tuple(int(getattr(self, n)) for n, _ in self._fields_)
@@ -58,27 +58,28 @@ DEFAULT_EXACT_ROUNDS = 1
 
 def make_tuning(t) -> "Tuning":
     """A Tuning from a Tuning or a tuple of its fields (the trailing exact_rounds,
-    verify_seeds, chunk_reads, workers and request_top may be left out: 1, 0, 0, 0 and 0)."""
+    verify_seeds, chunk_reads, workers, request_top and pass1_max_len may be left out: 1, 0,
+    0, 0, 0 and 0)."""
     if isinstance(t, Tuning):
         return t
     t = tuple(int(x) for x in t)
     if len(t) == 4:
         t = t + (DEFAULT_EXACT_ROUNDS,)
-    t = t + (0,) * (9 - len(t))
+    t = t + (0,) * (10 - len(t))
     return Tuning(*t)
 
 
 def set_tuning(pass1_seeds: int, pass1_limit: int, final_limit: int = 0, lane_max_len: int = 0,
                exact_rounds: int = DEFAULT_EXACT_ROUNDS, verify_seeds: int = 0, chunk_reads: int = 0,
-               workers: int = 0, request_top: int = 0):
+               workers: int = 0, request_top: int = 0, pass1_max_len: int = 0):
     """Output-invariant pass schedule and verify tiling (see snap_set_tuning); 0 = no cap."""
     _check(lib().snap_set_tuning(ctypes.byref(Tuning(pass1_seeds, pass1_limit, final_limit, lane_max_len,
                                                      exact_rounds, verify_seeds, chunk_reads, workers,
-                                                     request_top))),
+                                                     request_top, pass1_max_len))),
            "snap_set_tuning")
 
 
-def get_tuning() -> tuple[int, int, int, int, int, int, int, int, int]:
+def get_tuning() -> tuple[int, int, int, int, int, int, int, int, int, int]:
     t = Tuning()
     _check(lib().snap_get_tuning(ctypes.byref(t)), "snap_get_tuning")
     return t.astuple()

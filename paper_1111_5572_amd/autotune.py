@@ -72,7 +72,7 @@ def load_table(path: str = TABLE_PATH) -> dict:
 def lookup_entry(lengths: np.ndarray, batched: bool, path: str = TABLE_PATH):
     """The recorded entry (tuning, timings, sample) for this length class, or None."""
     e = load_table(path).get(("batched:" if batched else "plain:") + length_class(lengths))
-    if e and 4 <= len(e.get("tuning", ())) <= 9:
+    if e and 4 <= len(e.get("tuning", ())) <= 10:
         return e
     return None
 

@@ -2232,6 +2232,14 @@ struct HitRangePred {
     __host__ __device__ bool operator()(uint32_t r) const { return hits[r] > lo && hits[r] <= hi; }
 };
 
+// Reads longer than len_max (or, with `longer` false, the others).
+struct LenPred {
+    const int32_t *len;
+    int32_t len_max;
+    bool longer;
+    __device__ bool operator()(uint32_t r) const { return (len[r] > len_max) == longer; }
+};
+
 // Locations hit by one of the first seed slots (`bits`), below the chunk's location count.
 struct FirstSeedsPred {
     const uint32_t *mask;
@@ -2383,7 +2391,7 @@ void timed(const char *name, hipStream_t st, Launch launch) {
 // slots and verifies with limit pass1_limit; reads it cannot settle go to a
 // complete second pass.
 std::mutex g_tune_mu;
-snap_tuning g_tune = {5, 6, 6, 0, 1, 0, 0, 0, 0};   // stage-1 seeds and first limit, final first limit, lane-tile
+snap_tuning g_tune = {5, 6, 6, 0, 1, 0, 0, 0, 0, 0};   // stage-1 seeds and first limit, final first limit, lane-tile
                                            // read bound, exact-request rounds, first-verification seeds, ...
 
 
@@ -2439,7 +2447,7 @@ extern "C" snap_params snap_default_params(void) {
 extern "C" int32_t snap_max_limit(void) { return VERIFY_KMAX; }
 
 extern "C" int snap_set_tuning(const snap_tuning *t) {
-    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0 || t->chunk_reads < 0 || t->workers < 0 || t->request_top < 0 || t->request_top > REQUEST_TOP_MAX) return SNAP_EINVAL;
+    if (!t || t->pass1_seeds < 0 || t->pass1_limit < 0 || t->final_limit < 0 || t->lane_max_len < 0 || t->exact_rounds < 0 || t->verify_seeds < 0 || t->chunk_reads < 0 || t->workers < 0 || t->request_top < 0 || t->request_top > REQUEST_TOP_MAX || t->pass1_max_len < 0) return SNAP_EINVAL;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = *t;
     return SNAP_OK;
@@ -2492,7 +2500,7 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune = g_tune;
     }
-    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0 || tune.chunk_reads < 0 || tune.workers < 0 || tune.request_top < 0 || tune.request_top > REQUEST_TOP_MAX) return SNAP_EINVAL;
+    if (tune.pass1_seeds < 0 || tune.pass1_limit < 0 || tune.final_limit < 0 || tune.lane_max_len < 0 || tune.exact_rounds < 0 || tune.verify_seeds < 0 || tune.chunk_reads < 0 || tune.workers < 0 || tune.request_top < 0 || tune.request_top > REQUEST_TOP_MAX || tune.pass1_max_len < 0) return SNAP_EINVAL;
     const int request_top = tune.request_top > 0 ? tune.request_top : REQUEST_TOP_DEFAULT;
     const int lane_lmax = tune.lane_max_len > 0 ? std::min(tune.lane_max_len, LANE_LMAX) : LANE_LMAX;
     const int exact_rounds = tune.exact_rounds;
@@ -3120,6 +3128,36 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
     uint32_t *plist[2] = {pending, pending + n_reads};
     const uint32_t *list = nullptr;
     int64_t list_len = n_reads;
+    const int32_t split_len = tune.pass1_max_len;
+    if (nst == 2 && !batched && split_len > 0 && maxL > split_len && select_tmp_bytes(n_reads + 1) <= 8 * (size_t)PS) {
+        // reads longer than split_len need more round-0 seeds than the first stage probes
+        // before Algorithm 1 can stop: they take every seed slot in one complete pass over
+        // their own list (the first stage's limit); the others take the two stages
+        int64_t *cnt = wk[0].misc + 14;
+        size_t tb = select_tmp_bytes(n_reads + 1);
+        HIP_OK(select_idx(wk[0].hk, tb, n_reads, LenPred{lengths, split_len, false}, plist[0], cnt, st));
+        int64_t nshort = 0;
+        HIP_OK(hipMemcpyAsync(&nshort, cnt, 8, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        HIP_OK(select_idx(wk[0].hk, tb, n_reads, LenPred{lengths, split_len, true}, plist[0] + nshort, cnt + 1, st));
+        HIP_OK(hipStreamSynchronize(st));
+        pending_out = nullptr;
+        pend_count = 0;
+        int rc = run_pass(plist[0] + nshort, n_reads - nshort, NS, stages[0].cap, 1);
+        if (rc != SNAP_OK) return rc;
+        list = plist[0];
+        list_len = nshort;
+        pending_out = plist[1];
+        pend_count = 0;
+        if (list_len > 0) {
+            rc = run_pass(list, list_len, stages[0].seeds, stages[0].cap, 0);
+            if (rc != SNAP_OK) return rc;
+        }
+        list = plist[1];
+        list_len = pend_count;
+        if (list_len > 0) return run_pass(list, list_len, stages[1].seeds, stages[1].cap, 1);
+        return SNAP_OK;
+    }
     for (int k = 0; k < nst && list_len > 0; k++) {
         const bool last = (k == nst - 1);
         pending_out = plist[k & 1];

@@ -193,6 +193,39 @@ def test_request_top_invariance(snapgpu, oracle_mod, synth_mod, top):
         snapgpu.set_tuning(*old)
 
 
+@pytest.mark.parametrize("max_len,seeds,chunk", [(99, 5, 0), (100, 5, 0), (128, 5, 0), (249, 5, 0), (250, 5, 0),
+                                                   (128, 3, 1500), (128, 0, 0), (128, 6, 0)])
+def test_long_read_first_pass_invariance(snapgpu, oracle_mod, synth_mod, max_len, seeds, chunk):
+    """Reads longer than pass1_max_len take every seed slot in one complete pass over their own
+    list, the others the first and the final pass: outputs never change. 100 and 250 bp reads
+    at d_max 15, bounds on either side of both lengths and at them (a read of exactly that
+    length stays in the two passes), small chunks (several chunks a pass and two workers), and
+    no first stage at all (pass1_seeds 0: nothing to split)."""
+    from synth.workloads import HUMAN
+    w, g, reads = _world(synth_mod, HUMAN, 2_000_000, 8_000)
+    old = snapgpu.get_tuning()
+    try:
+        snapgpu.set_tuning(seeds, 7, 7, 0, 5, 0, chunk, 2, 4, max_len)
+        _check(snapgpu, oracle_mod, w, g, reads, f"pass1_max_len {max_len} seeds {seeds} chunk {chunk}")
+    finally:
+        snapgpu.set_tuning(*old)
+
+
+def test_long_read_first_pass_mixed_wave_tile(snapgpu, oracle_mod, synth_mod):
+    """The same on the batched recipe at reduced size (log-uniform 100 bp - 10 kb, d_max 8% of
+    the length): the long reads' complete pass runs the wave tile."""
+    from synth.workloads import BATCHED
+    w = BATCHED.scaled(genome_len=3_000_000, n_reads=300)
+    g = w.make_genome()
+    reads = w.make_reads(g)
+    old = snapgpu.get_tuning()
+    try:
+        snapgpu.set_tuning(5, 6, 6, 0, 1, 0, 0, 0, 0, 300)
+        _check(snapgpu, oracle_mod, w, g, reads, "pass1_max_len 300, batched recipe")
+    finally:
+        snapgpu.set_tuning(*old)
+
+
 def test_batch_composition_invariance(snapgpu, synth_mod):
     """A read's output does not depend on the other reads in the batch or their order."""
     from synth.workloads import MID
