@@ -2687,8 +2687,10 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         HIP_OK(hipEventRecord(leases[w - 1]->ev, st));
         HIP_OK(hipStreamWaitEvent(wk[w].st, leases[w - 1]->ev, 0));
     }
-    // one pass over a list of reads (all reads, or the ones an earlier pass left)
-    auto run_pass = [&](const uint32_t *ridx, int64_t list_len, int NSp, int Kcap, int final_pass) -> int {
+    // one pass over a list of reads (all reads, or the ones an earlier pass left); `first`:
+    // a pass of the first stage (its reads counted as the batch's, else as reads a first
+    // pass left to a later one)
+    auto run_pass = [&](const uint32_t *ridx, int64_t list_len, int NSp, int Kcap, int final_pass, bool first) -> int {
         const int Kp = std::min(Kmax, Kcap);
         // lane-per-location tile: reads up to LANE_LMAX bases with limits up to LANE_KMAX
         const int lane_L = std::min(maxL, lane_lmax), lane_K = std::min(Kp, LANE_KMAX);
@@ -3074,14 +3076,14 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
                 HIP_OK(hipStreamSynchronize(st));
                 std::lock_guard<std::mutex> g(g_prof_mu);
                 g_ctr.passes += 1;
-                g_ctr.reads += (ridx == nullptr) ? nr : 0;
+                g_ctr.reads += first ? nr : 0;
                 g_ctr.seed_slots += nr * NSp;
                 g_ctr.hits += total;
                 g_ctr.locations += ncand;
                 g_ctr.lv_steps += (int64_t)ssum;
                 g_ctr.lv_steps_first += (int64_t)sfirst;
                 g_ctr.dup_aliases += (int64_t)nal;
-                if (ridx) g_ctr.second_pass_reads += nr;
+                if (!first) g_ctr.second_pass_reads += nr;
             }
             r0 += nr;
           }
@@ -3143,26 +3145,26 @@ int align_impl(const snap_index *ix, const uint8_t *reads, const int32_t *length
         HIP_OK(hipStreamSynchronize(st));
         pending_out = nullptr;
         pend_count = 0;
-        int rc = run_pass(plist[0] + nshort, n_reads - nshort, NS, stages[0].cap, 1);
+        int rc = run_pass(plist[0] + nshort, n_reads - nshort, NS, stages[0].cap, 1, true);
         if (rc != SNAP_OK) return rc;
         list = plist[0];
         list_len = nshort;
         pending_out = plist[1];
         pend_count = 0;
         if (list_len > 0) {
-            rc = run_pass(list, list_len, stages[0].seeds, stages[0].cap, 0);
+            rc = run_pass(list, list_len, stages[0].seeds, stages[0].cap, 0, true);
             if (rc != SNAP_OK) return rc;
         }
         list = plist[1];
         list_len = pend_count;
-        if (list_len > 0) return run_pass(list, list_len, stages[1].seeds, stages[1].cap, 1);
+        if (list_len > 0) return run_pass(list, list_len, stages[1].seeds, stages[1].cap, 1, false);
         return SNAP_OK;
     }
     for (int k = 0; k < nst && list_len > 0; k++) {
         const bool last = (k == nst - 1);
         pending_out = plist[k & 1];
         pend_count = 0;
-        int rc = run_pass(list, list_len, stages[k].seeds, stages[k].cap, last ? 1 : 0);
+        int rc = run_pass(list, list_len, stages[k].seeds, stages[k].cap, last ? 1 : 0, k == 0);
         if (rc != SNAP_OK) return rc;
         if (last) break;
         list = plist[k & 1];

@@ -211,6 +211,28 @@ def test_long_read_first_pass_invariance(snapgpu, oracle_mod, synth_mod, max_len
         snapgpu.set_tuning(*old)
 
 
+def test_long_read_first_pass_counters(snapgpu, oracle_mod, synth_mod):
+    """With the long reads' complete pass, the profiling counters still count every read of
+    the batch once as the batch's and only the short reads a first pass left as later-pass
+    reads (both first-stage passes run over read lists)."""
+    from synth.workloads import HUMAN
+    w, g, reads = _world(synth_mod, HUMAN, 2_000_000, 8_000)
+    n_long = int((reads.lengths > 128).sum())
+    old = snapgpu.get_tuning()
+    try:
+        snapgpu.set_tuning(5, 7, 7, 0, 5, 0, 1500, 2, 4, 128)
+        snapgpu.profile_begin()
+        _check(snapgpu, oracle_mod, w, g, reads, "pass1_max_len 128, counters")
+        ctr = snapgpu.profile_counters()
+        snapgpu.profile_end()
+        say(f"counters {ctr}; long reads {n_long}")
+        assert 0 < n_long < reads.n
+        assert ctr["reads"] == reads.n, ctr
+        assert 0 <= ctr["second_pass_reads"] <= reads.n - n_long, ctr
+    finally:
+        snapgpu.set_tuning(*old)
+
+
 def test_long_read_first_pass_mixed_wave_tile(snapgpu, oracle_mod, synth_mod):
     """The same on the batched recipe at reduced size (log-uniform 100 bp - 10 kb, d_max 8% of
     the length): the long reads' complete pass runs the wave tile."""
