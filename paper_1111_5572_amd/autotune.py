@@ -3,8 +3,9 @@
 The knobs (snap_tuning): the seeds and verify limit of the first pass, the first
 verify limit of the final pass, the verify tile bound (reads up to that length
 get one lane per location, longer ones a wave per location) and the number of
-replay rounds that ask for single locations, and the seed slots whose locations
-the first verification covers. Outputs do
+replay rounds that ask for single locations, the seed slots whose locations
+the first verification covers, and, for reads of mixed lengths, the length above
+which reads take every seed slot in one complete pass. Outputs do
 not depend on them; only the time does. The tuner aligns a sample of the batch
 with each candidate, keeps the fastest, and records it in a JSON table keyed by
 the batch's read-length class.
@@ -52,6 +53,20 @@ CANDIDATES = [
 ]
 
 
+def candidates_for(lengths: np.ndarray, batched: bool, base=None) -> list:
+    """The candidates for a batch: `base` (CANDIDATES), and for plain calls on reads of mixed
+    lengths two of them again with pass1_max_len at each quartile of the lengths below the
+    longest (the reads above it then take every seed slot in one complete pass)."""
+    cands = list(base or CANDIDATES)
+    if batched or len(lengths) == 0:
+        return cands
+    top = int(np.max(lengths))
+    cuts = sorted({int(np.percentile(lengths, q)) for q in (25, 50, 75)} - {top})
+    for b in ((5, 6, 6, 0, 1, 0), (5, 7, 7, 0, 5, 0)):
+        cands += [b + (0, 0, 0, cut) for cut in cuts if 0 < cut < top]
+    return cands
+
+
 def length_class(lengths: np.ndarray) -> str:
     """Key of the tuning table: read-length span of the batch in powers of two."""
     if len(lengths) == 0:
@@ -94,7 +109,7 @@ def tune(index, reads_dev, lengths_dev, d_max: int, params=None, batched: bool =
     nb = int(lengths_host[:n].astype(np.int64).sum())
     rb, ln = reads_dev[:nb], lengths_dev[:n]
     max_len = int(lengths_host[:n].max()) if n else 0
-    candidates = candidates or CANDIDATES
+    candidates = candidates or candidates_for(lengths_host[:n], batched)
     out = None
     timings = {}
     stream = torch.cuda.current_stream()

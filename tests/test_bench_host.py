@@ -119,6 +119,23 @@ def test_tuning_table_lookup(tmp_path):
     assert autotune.lookup(lens, batched=False) is not None
 
 
+def test_autotune_candidates_for_mixed_lengths():
+    """Plain calls on reads of mixed lengths also try pass1_max_len at the length quartiles
+    below the longest read; one length, or the batched form, adds nothing."""
+    sys.path.insert(0, ROOT)
+    from paper_1111_5572_amd import autotune
+    base = len(autotune.CANDIDATES)
+    mixed = np.concatenate([np.full(50, 100), np.full(50, 250)]).astype(np.int32)
+    c = autotune.candidates_for(mixed, batched=False)
+    extra = c[base:]
+    assert extra and all(len(x) == 10 for x in extra)
+    assert sorted({x[9] for x in extra}) == [100, 175]
+    assert all(0 < x[9] < 250 for x in extra)
+    assert len(autotune.candidates_for(np.full(100, 100, np.int32), batched=False)) == base
+    assert len(autotune.candidates_for(mixed, batched=True)) == base
+    assert len(autotune.candidates_for(np.array([], np.int32), batched=False)) == base
+
+
 def test_accuracy_grid_dmax(bench):
     # 1.5 times the expected edits, at least 8, at most the largest limit minus c - 1
     assert bench.grid_dmax(100, 0.02) == 8
