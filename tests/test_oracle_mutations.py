@@ -1,7 +1,9 @@
-"""The oracle's pins catch plausible mistakes in Algorithm 1: each one-line change below
-(a wrong limit case, a boundary test off by one, a dropped orientation, a wrong tie-break,
-a shorter text window, an early return where the paper has none) is applied to a copy of
-oracle.c, and the copy must fail at least one of the oracle's CPU pin tests."""
+"""The oracle's pins catch plausible mistakes in Algorithm 1 and in the readings of the
+strided index and the exact-duplicate classes: each one-line change below (a wrong limit
+case, a boundary test off by one, a dropped orientation, a wrong tie-break, a shorter text
+window, an early return where the paper has none, an N test over one seed of a slot, t over
+incomplete slots, a class on a shorter window or with the wrong representative) is applied
+to a copy of oracle.c, and the copy must fail at least one of the oracle's CPU pin tests."""
 import os
 import shutil
 import subprocess
@@ -38,6 +40,19 @@ MUTATIONS = [
      "if (x->d < y->d || (x->d == y->d && (x->p < y->p || (x->p == y->p && x->strand > y->strand)))) bi = j;"),
     ("text window of L + limit bases",
      "int64_t want = (int64_t)L + (lim > 0 ? lim : 0);", "int64_t want = (int64_t)L + (lim > 0 ? lim - 1 : 0);"),
+    # the strided index (reading S1)
+    ("a slot is skipped for an N in any of its seeds, not only the first",
+     "if (has_n(w->fwd + o, s + np - 1)) { stt->seeds_with_n++; continue; }",
+     "if (has_n(w->fwd + o, s)) { stt->seeds_with_n++; continue; }"),
+    ("t counts a round-0 slot only when all its seeds fit the read",
+     "if (o % s == 0 && np == stride) t++;", "if (o % s == 0) t++;"),
+    # exact-duplicate classes (reading S2)
+    ("a class needs the whole W-base window identical",
+     "if (memcmp(codes + order[k], codes + order[k - 1], (size_t)W) == 0) rep[order[k]] = rep[order[k - 1]];",
+     "if (memcmp(codes + order[k], codes + order[k - 1], (size_t)W - 1) == 0) rep[order[k]] = rep[order[k - 1]];"),
+    ("a class's representative is its smallest position, not the previous member",
+     "if (memcmp(codes + order[k], codes + order[k - 1], (size_t)W) == 0) rep[order[k]] = rep[order[k - 1]];",
+     "if (memcmp(codes + order[k], codes + order[k - 1], (size_t)W) == 0) rep[order[k]] = order[k - 1];"),
     ("no early return while scoring the remaining locations",
      "                score(ix, w, &st, k, L, dmax, pr, stt, lg);\n            }",
      "                score(ix, w, &st, k, L, dmax, pr, stt, lg);\n"
@@ -45,7 +60,7 @@ MUTATIONS = [
 ]
 
 PIN_TESTS = ["tests/test_oracle_algorithm1.py", "tests/test_oracle_branches.py", "tests/test_oracle_pins.py",
-             "tests/test_oracle_invariants.py", "tests/test_oracle_strided.py"]
+             "tests/test_oracle_invariants.py", "tests/test_oracle_strided.py", "tests/test_oracle_dups.py"]
 
 
 @pytest.mark.parametrize("what,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
