@@ -245,8 +245,9 @@ int32_t snap_max_limit(void);
  * duplicate classes, verify_seeds 0) the location Algorithm 1 scores first is verified
  * at the read's full limit before the others, and when its distance d1 is within
  * d_max(L) the others are verified with min(limit, d1 + c - 1). Only reads that need
- * more seeds than the first pass probed go on to the final pass. 0 in a field means "no cap" (no first pass when pass1_seeds and
- * pass1_limit are both 0). Outputs never depend on these values.
+ * more seeds than the first pass probed go on to the final pass. 0 in a field means
+ * "no cap" (no first pass when pass1_seeds and pass1_limit are both 0). Outputs never
+ * depend on these values.
  */
 typedef struct {
     int32_t pass1_seeds;
